@@ -1,0 +1,154 @@
+/*
+ * bpsf.h - C ABI of the MI355X (gfx950) BP-SF decoder library (libbpsf.so).
+ *
+ * BP-SF ("Fully Parallelized BP Decoding for Quantum LDPC Codes Can
+ * Outperform BP-OSD", arXiv 2507.00254) decodes a syndrome s of a binary
+ * parity-check matrix H (the decoding problem of Section II-B: find e with
+ * e H^T = s) in three steps (Algorithm 1):
+ *   1. flooding normalized min-sum BP (Section II-B, steps 1-4, Eq. (c2v))
+ *      while counting how often every hard decision flips;
+ *   2. if BP does not reproduce s within max_iter iterations, take the k
+ *      most-flipped bits Phi and form trial vectors t over Phi;
+ *   3. decode every trial syndrome s' = s + t H^T with an independent short
+ *      BP and return e' + t for a successful trial (the lightest one, or the
+ *      lowest-index one, see bpsf_params.select_mode).
+ *
+ * Conventions for every entry point:
+ *   - return 0 on success or a negative BPSF_E* code; bpsf_last_error() then
+ *     returns a message for the calling thread; nothing else reports errors
+ *     and no C++ exception crosses the ABI;
+ *   - "device" pointers are HIP device memory of the current device, "host"
+ *     pointers are ordinary host memory; every buffer is owned by the caller
+ *     and must stay valid until the work enqueued on `stream` has completed;
+ *   - `stream` is a hipStream_t (NULL = the default stream); decoding is
+ *     asynchronous on that stream and outputs are valid once it synchronizes;
+ *   - a code handle owns device copies of the code tables and a scratch area
+ *     reused by every decode call on it: calls on one handle must be issued
+ *     on one stream (or otherwise ordered); handles are independent.
+ */
+#ifndef BPSF_H
+#define BPSF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BPSF_OK 0
+#define BPSF_EINVAL (-1)   /* bad shape, pointer or parameter */
+#define BPSF_ENOMEM (-2)   /* device memory allocation failed */
+#define BPSF_ENOTSUP (-3)  /* the code's shape has no compiled kernel tile */
+#define BPSF_EDEVICE (-4)  /* a HIP call failed */
+
+/* Trial vector sets (Algorithm 1, combinations(Phi, w_max)). */
+#define BPSF_TRIALS_ALL_SUBSETS 0   /* all 2^k subsets of Phi; trial index = mask, bit j <-> Phi[j] */
+#define BPSF_TRIALS_WEIGHT_LE 1     /* subsets of weight 1..w_max, by weight, then combination order */
+
+/* Result selection among successful trials (Section IV). */
+#define BPSF_SELECT_MIN_WEIGHT 0    /* lightest e' + t; ties to the lower trial index */
+#define BPSF_SELECT_FIRST 1         /* lowest successful trial index */
+
+/* bpsf_params.flags (test and study options) */
+#define BPSF_FLAG_NO_EARLY_STOP 1   /* run max_iter iterations even after e H^T = s */
+#define BPSF_FLAG_FORCE_PP 2        /* run the trials even when the first BP succeeded */
+
+#define BPSF_PREC_FP32 0            /* messages in float */
+#define BPSF_PREC_FP64 1            /* messages in double */
+
+typedef struct bpsf_code_s* bpsf_code;
+
+typedef struct {
+  int32_t max_iter;       /* i_max of the first BP, 1..255 */
+  int32_t cand_max_iter;  /* i_max of every trial BP, 1..4095 */
+  int32_t k;              /* |Phi|, 0..16; 0 = plain BP (no trials) */
+  int32_t cand_mode;      /* BPSF_TRIALS_* */
+  int32_t w_max;          /* BPSF_TRIALS_WEIGHT_LE: largest trial weight, 1..k */
+  int32_t select_mode;    /* BPSF_SELECT_* */
+  double alpha;           /* > 0: fixed normalization of c2v (e.g. 0.625); 0: alpha_i = 1 - 2^-i */
+  int32_t flags;          /* BPSF_FLAG_* */
+  int32_t precision;      /* BPSF_PREC_* */
+} bpsf_params;
+
+typedef struct {
+  int64_t main_iterations;   /* first-BP iterations summed over the shots of the last call */
+  int64_t trial_iterations;  /* trial-BP iterations summed over every trial run */
+  int64_t rerun_iterations;  /* iterations of the re-runs that emit winning trials */
+  int64_t failed_shots;      /* shots whose first BP failed (or all shots with FORCE_PP, k > 0) */
+  int64_t converged_trials;  /* trials that reproduced their syndrome */
+  int64_t errors;            /* internal consistency failures (must be 0) */
+} bpsf_stats;
+
+/*
+ * Load a parity-check matrix H (M x N, entries 0/1) given by rows:
+ * row_ptr[M+1] and col_idx[row_ptr[M]] (host, int32; column indices of each
+ * row strictly ascending and in [0, N)). The Tanner graph is the bipartite
+ * graph of H (Section II-B): bits are columns, checks are rows. Builds the
+ * device tables (edge layouts) on the current device; *out receives a handle
+ * to free with bpsf_free_code. Fails with BPSF_ENOTSUP when the row and column
+ * weights have no compiled kernel tile (currently regular codes, row weight 6,
+ * column weight 3, up to 288 bits, e.g. the bivariate-bicycle codes of
+ * Appendix A).
+ */
+int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, int32_t N, bpsf_code* out);
+
+/* Release a handle and its device memory (NULL is ignored). Synchronizes the device. */
+void bpsf_free_code(bpsf_code code);
+
+/*
+ * Decode `shots` syndromes.
+ *   syndromes   device, uint8 [shots][M], each entry 0 or 1 (only bit 0 is read)
+ *   priors      host, double [N], error probability p_v of every bit, each in
+ *               (0, 1); channel LLR l_v = log((1 - p_v) / p_v) (Section II-B
+ *               step 1) is computed on the host in double and cached on the
+ *               device for the next call with the same priors
+ *   params      host; see bpsf_params
+ *   corrections device, uint8 [shots][N]: the estimate e (0/1); when no trial
+ *               succeeds it is the first BP's last hard decision
+ *   converged   device, uint8 [shots]: 1 iff corrections[i] H^T = s_i
+ *   iterations  device, int32 [shots]: first-BP iterations, plus the winning
+ *               trial's iterations when a trial produced the result
+ *   stream      hipStream_t
+ * shots may be 0. Scratch grows with the largest shot count seen and is
+ * reused; the call allocates device memory only when it must grow.
+ */
+int bpsf_decode(bpsf_code code, const uint8_t* syndromes, const double* priors, int64_t shots,
+                const bpsf_params* params, uint8_t* corrections, uint8_t* converged, int32_t* iterations,
+                void* stream);
+
+/* Work counters of the last bpsf_decode on `code` (host out). Waits for `stream`. */
+int bpsf_last_stats(bpsf_code code, void* stream, bpsf_stats* out);
+
+/*
+ * Debug entry point: plain BP (no trials) on one syndrome, recording every
+ * iteration. syndrome host uint8 [M]; priors host double [N]; params as for
+ * bpsf_decode (k, cand_* ignored). lout_trace host Real [max_iter][N] and
+ * c2v_trace host Real [max_iter][M*W] (Real = float or double by
+ * params->precision; c2v in row order of H, W = row weight) may be NULL.
+ * hard_out host uint8 [N]; *iters_out, *converged_out as for bpsf_decode.
+ * Synchronous; allocates and frees its own device buffers.
+ */
+int bpsf_bp_trace(bpsf_code code, const uint8_t* syndrome, const double* priors, const bpsf_params* params,
+                  void* lout_trace, void* c2v_trace, uint8_t* hard_out, int32_t* iters_out,
+                  uint8_t* converged_out);
+
+/*
+ * Trial vectors the parameters produce (host only, no device needed): returns
+ * their number n (or a negative BPSF_E* code) and, when masks_out is not NULL,
+ * writes min(n, cap) k-bit masks in trial order (bit j <-> Phi[j], Phi[0] the
+ * most-flipped bit) to the host array masks_out.
+ */
+int64_t bpsf_num_trials(const bpsf_params* params, uint32_t* masks_out, int64_t cap);
+
+/* Shape of a loaded code: M, N, edges, row weight, column weight (host outs, any may be NULL). */
+int bpsf_code_info(bpsf_code code, int32_t* M, int32_t* N, int32_t* edges, int32_t* row_weight,
+                   int32_t* col_weight);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* bpsf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BPSF_H */

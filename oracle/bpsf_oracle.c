@@ -218,10 +218,9 @@ static int bp_run(const graph *g, const uint8_t *s, const real *L, const oracle_
             for (int e = g->row_ptr[c]; e < g->row_ptr[c + 1]; e++) par ^= w->hard[g->col_idx[e]];
             if (par) ok = 0;
         }
-        if (ok) {
-            *converged = 1;
-            if (!(prm->flags & OR_NO_EARLY_STOP)) return it;
-        }
+        /* The flag describes the hard decision that is returned. */
+        *converged = ok;
+        if (ok && !(prm->flags & OR_NO_EARLY_STOP)) return it;
     }
     return max_iter;
 }

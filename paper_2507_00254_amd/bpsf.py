@@ -1,0 +1,202 @@
+"""Python binding of ``libbpsf.so`` (argument marshalling only).
+
+Every decoding step runs in the library's HIP kernels; PyTorch provides device
+memory and streams. The functions keep the C ABI's names (``include/bpsf.h``);
+:class:`Decoder` is a convenience wrapper around them. Importing this module
+loads the library and raises if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbpsf.so")
+
+BPSF_OK, BPSF_EINVAL, BPSF_ENOMEM, BPSF_ENOTSUP, BPSF_EDEVICE = 0, -1, -2, -3, -4
+TRIALS_ALL_SUBSETS, TRIALS_WEIGHT_LE = 0, 1
+SELECT_MIN_WEIGHT, SELECT_FIRST = 0, 1
+FLAG_NO_EARLY_STOP, FLAG_FORCE_PP = 1, 2
+PREC_FP32, PREC_FP64 = 0, 1
+
+
+class bpsf_params(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("cand_max_iter", C.c_int32), ("k", C.c_int32),
+                ("cand_mode", C.c_int32), ("w_max", C.c_int32), ("select_mode", C.c_int32),
+                ("alpha", C.c_double), ("flags", C.c_int32), ("precision", C.c_int32)]
+
+
+class bpsf_stats(C.Structure):
+    _fields_ = [("main_iterations", C.c_int64), ("trial_iterations", C.c_int64),
+                ("rerun_iterations", C.c_int64), ("failed_shots", C.c_int64),
+                ("converged_trials", C.c_int64), ("errors", C.c_int64)]
+
+
+class BpsfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libbpsf error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2507_00254_amd/build.py "
+                          "(or __graft_entry__.build())")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    P = C.POINTER
+    lib.bpsf_load_code.argtypes = [P(i32), P(i32), i32, i32, P(vp)]
+    lib.bpsf_free_code.argtypes = [vp]
+    lib.bpsf_free_code.restype = None
+    lib.bpsf_decode.argtypes = [vp, vp, P(C.c_double), i64, P(bpsf_params), vp, vp, vp, vp]
+    lib.bpsf_last_stats.argtypes = [vp, vp, P(bpsf_stats)]
+    lib.bpsf_bp_trace.argtypes = [vp, P(C.c_uint8), P(C.c_double), P(bpsf_params), vp, vp, P(C.c_uint8),
+                                  P(i32), P(C.c_uint8)]
+    lib.bpsf_num_trials.argtypes = [P(bpsf_params), P(C.c_uint32), i64]
+    lib.bpsf_num_trials.restype = i64
+    lib.bpsf_code_info.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(i32)]
+    lib.bpsf_last_error.argtypes = []
+    lib.bpsf_last_error.restype = C.c_char_p
+    return lib
+
+
+LIB = _load()
+
+
+def _check(rc):
+    if rc != 0:
+        raise BpsfError(rc, LIB.bpsf_last_error().decode())
+    return rc
+
+
+def make_params(max_iter=100, cand_max_iter=20, k=6, cand_mode=TRIALS_ALL_SUBSETS, w_max=1,
+                select_mode=SELECT_MIN_WEIGHT, alpha=0.625, flags=0, precision=PREC_FP32) -> bpsf_params:
+    return bpsf_params(max_iter, cand_max_iter, k, cand_mode, w_max, select_mode, float(alpha), flags, precision)
+
+
+def _csr(h):
+    if isinstance(h, tuple):
+        row_ptr, col_idx, m, n = h
+    else:
+        h = np.asarray(h, dtype=np.uint8)
+        rows, cols = np.nonzero(h)
+        m, n = h.shape
+        row_ptr = np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=m))])
+        col_idx = cols
+    return (np.ascontiguousarray(row_ptr, dtype=np.int32), np.ascontiguousarray(col_idx, dtype=np.int32),
+            int(m), int(n))
+
+
+def bpsf_load_code(h) -> int:
+    """H as a dense 0/1 array or ``(row_ptr, col_idx, M, N)``; returns the handle."""
+    row_ptr, col_idx, m, n = _csr(h)
+    out = C.c_void_p()
+    _check(LIB.bpsf_load_code(row_ptr.ctypes.data_as(C.POINTER(C.c_int32)),
+                              col_idx.ctypes.data_as(C.POINTER(C.c_int32)), m, n, C.byref(out)))
+    return out.value
+
+
+def bpsf_free_code(handle) -> None:
+    LIB.bpsf_free_code(handle)
+
+
+def bpsf_num_trials(params: bpsf_params) -> np.ndarray:
+    n = LIB.bpsf_num_trials(C.byref(params), None, 0)
+    _check(n if n < 0 else 0)
+    masks = np.zeros(max(n, 1), np.uint32)
+    LIB.bpsf_num_trials(C.byref(params), masks.ctypes.data_as(C.POINTER(C.c_uint32)), n)
+    return masks[:n]
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def bpsf_decode(handle, syndromes, priors, params: bpsf_params, corrections, converged, iterations,
+                stream=None) -> None:
+    """Enqueue a decode. ``syndromes`` uint8 [shots, M], ``corrections`` uint8
+    [shots, N], ``converged`` uint8 [shots], ``iterations`` int32 [shots] are
+    torch tensors on the GPU; ``priors`` is a host array of N probabilities."""
+    pri = np.ascontiguousarray(priors, dtype=np.float64)
+    shots = int(syndromes.shape[0])
+    for t in (syndromes, corrections, converged, iterations):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("device tensors must be contiguous CUDA (HIP) tensors")
+    _check(LIB.bpsf_decode(C.c_void_p(handle), C.c_void_p(syndromes.data_ptr()),
+                           pri.ctypes.data_as(C.POINTER(C.c_double)), shots, C.byref(params),
+                           C.c_void_p(corrections.data_ptr()), C.c_void_p(converged.data_ptr()),
+                           C.c_void_p(iterations.data_ptr()), _stream_ptr(stream)))
+
+
+def bpsf_last_stats(handle, stream=None) -> dict:
+    st = bpsf_stats()
+    _check(LIB.bpsf_last_stats(C.c_void_p(handle), _stream_ptr(stream), C.byref(st)))
+    return {f: getattr(st, f) for f, _ in bpsf_stats._fields_}
+
+
+def bpsf_code_info(handle) -> dict:
+    vals = [C.c_int32() for _ in range(5)]
+    _check(LIB.bpsf_code_info(C.c_void_p(handle), *[C.byref(v) for v in vals]))
+    return dict(zip(("M", "N", "edges", "row_weight", "col_weight"), (v.value for v in vals)))
+
+
+def bpsf_bp_trace(handle, syndrome, priors, params: bpsf_params):
+    """Plain BP on one syndrome with every iteration's marginals and c2v messages."""
+    info = bpsf_code_info(handle)
+    m, n, w = info["M"], info["N"], info["row_weight"]
+    dt = np.float64 if params.precision == PREC_FP64 else np.float32
+    lout = np.zeros((params.max_iter, n), dt)
+    c2v = np.zeros((params.max_iter, m * w), dt)
+    hard = np.zeros(n, np.uint8)
+    it = C.c_int32()
+    conv = C.c_uint8()
+    s = np.ascontiguousarray(syndrome, dtype=np.uint8)
+    pri = np.ascontiguousarray(np.broadcast_to(np.asarray(priors, np.float64), (n,)))
+    _check(LIB.bpsf_bp_trace(C.c_void_p(handle), s.ctypes.data_as(C.POINTER(C.c_uint8)),
+                             pri.ctypes.data_as(C.POINTER(C.c_double)), C.byref(params),
+                             lout.ctypes.data_as(C.c_void_p), c2v.ctypes.data_as(C.c_void_p),
+                             hard.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(it), C.byref(conv)))
+    k = it.value
+    return {"hard": hard, "iterations": k, "converged": conv.value, "trace_lout": lout[:k], "trace_c2v": c2v[:k]}
+
+
+class Decoder:
+    """A loaded code plus output buffers; ``decode`` returns torch tensors."""
+
+    def __init__(self, h, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.handle = bpsf_load_code(h)
+        info = bpsf_code_info(self.handle)
+        self.M, self.N = info["M"], info["N"]
+
+    def decode(self, syndromes, priors, params: bpsf_params, stream=None, out=None):
+        torch = self.torch
+        shots = int(syndromes.shape[0])
+        if out is None:
+            out = (torch.empty((shots, self.N), dtype=torch.uint8, device=syndromes.device),
+                   torch.empty((shots,), dtype=torch.uint8, device=syndromes.device),
+                   torch.empty((shots,), dtype=torch.int32, device=syndromes.device))
+        pri = np.broadcast_to(np.asarray(priors, np.float64), (self.N,))
+        bpsf_decode(self.handle, syndromes, pri, params, out[0], out[1], out[2], stream)
+        return out
+
+    def stats(self, stream=None):
+        return bpsf_last_stats(self.handle, stream)
+
+    def close(self):
+        if self.handle:
+            bpsf_free_code(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

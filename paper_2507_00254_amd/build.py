@@ -1,0 +1,53 @@
+"""Build ``libbpsf.so`` (HIP, gfx950) in-tree with hipcc.
+
+The kernels are compiled with ``-ffp-contract=off`` (no fused multiply-add,
+so float arithmetic matches a plain C evaluation of the same expressions) and
+``-fno-honor-nans`` (no NaN can reach the message arithmetic; this lets min and
+max take their operands without canonicalization). The host runtime is
+compiled without ``-fno-honor-nans`` because it validates user input.
+Packed FP32 instructions are disabled for device code.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libbpsf.so")
+ARCH = os.environ.get("BPSF_OFFLOAD_ARCH", "gfx950")
+
+COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-variable",
+          "-Wno-unused-but-set-variable"]
+UNITS = [("bpsf_kernels.hip", ["-fno-honor-nans"]), ("bpsf_api.hip", [])]
+
+
+def sources():
+    return [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC))
+            if f.endswith((".hip", ".h"))] + [os.path.join(os.path.dirname(HERE), "include", "bpsf.h")]
+
+
+def build(verbose: bool = False) -> str:
+    bdir = os.path.join(HERE, "_build")
+    os.makedirs(bdir, exist_ok=True)
+    objs = []
+    for src, extra in UNITS:
+        obj = os.path.join(bdir, src.replace(".hip", ".o"))
+        cmd = ["hipcc", *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,436 @@
+// Host runtime of the BP-SF library: code loading (edge layouts), parameter
+// checks, channel LLRs, trial-vector tables, scratch management and the launch
+// sequence of the three decode phases. C ABI declared in include/bpsf.h.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/bpsf.h"
+#include "bpsf_internal.h"
+#include "bpsf_tiles.h"
+
+using namespace bpsf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_OK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) return fail(BPSF_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+const TileDesc kTiles[] = {
+#define BPSF_TILE_DESC(D_, IC_, IV_, W_, DV_) {D_, IC_, IV_, W_, DV_},
+    BPSF_TILE_LIST(BPSF_TILE_DESC)
+#undef BPSF_TILE_DESC
+};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+  // grow-only; contents are not preserved
+  int ensure(size_t want)
+  {
+    if (want <= bytes) return 0;
+    if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
+    if (hipMalloc(&p, want) != hipSuccess) { p = nullptr; return -1; }
+    bytes = want;
+    return 0;
+  }
+};
+
+}  // namespace
+
+struct bpsf_code_s {
+  int device = 0;
+  int M = 0, N = 0, E = 0, W = 0, DV = 0;
+  int cus = 0;
+  DevBuf var_chk, var_pos, ell_col;
+  // channel LLR cache
+  std::vector<double> priors;
+  DevBuf llr32, llr64;
+  // trial masks cache
+  int masks_k = -1, masks_mode = -1, masks_wmax = -1, n_trials = 0;
+  DevBuf masks;
+  // scratch
+  DevBuf records, keys, counters;
+  std::mutex mu;
+};
+
+namespace {
+
+int pick_tile(const bpsf_code_s* c, TileDesc* out)
+{
+  int best = -1;
+  for (int i = 0; i < (int)(sizeof kTiles / sizeof kTiles[0]); ++i) {
+    const TileDesc& t = kTiles[i];
+    if (t.W != c->W || t.DV != c->DV) continue;
+    const int G = 64 / t.D;
+    if ((c->M + G - 1) / G > t.IC || (c->N + G - 1) / G > t.IV) continue;
+    if (c->N * t.DV > 65535) continue;
+    if (best < 0) { best = i; continue; }
+    const TileDesc& b = kTiles[best];
+    // more slots first, then fewer padded items
+    if (t.D > b.D || (t.D == b.D && t.IC * t.IV < b.IC * b.IV)) best = i;
+  }
+  if (best < 0) return -1;
+  *out = kTiles[best];
+  return 0;
+}
+
+// Trial vectors of Algorithm 1 as k-bit masks over Phi, in trial order.
+std::vector<uint32_t> trial_masks(int k, int mode, int w_max)
+{
+  std::vector<uint32_t> m;
+  if (k <= 0) return m;
+  if (mode == BPSF_TRIALS_ALL_SUBSETS) {
+    m.resize((size_t)1 << k);
+    for (size_t i = 0; i < m.size(); ++i) m[i] = (uint32_t)i;
+    return m;
+  }
+  for (int w = 1; w <= w_max; ++w) {
+    std::vector<int> pos(w);
+    for (int j = 0; j < w; ++j) pos[j] = j;
+    for (;;) {
+      uint32_t x = 0;
+      for (int j = 0; j < w; ++j) x |= 1u << pos[j];
+      m.push_back(x);
+      int j = w - 1;
+      while (j >= 0 && pos[j] == k - w + j) --j;
+      if (j < 0) break;
+      ++pos[j];
+      for (int i = j + 1; i < w; ++i) pos[i] = pos[i - 1] + 1;
+    }
+  }
+  return m;
+}
+
+int check_params(const bpsf_params* p)
+{
+  if (!p) return fail(BPSF_EINVAL, "params is NULL");
+  if (p->max_iter < 1 || p->max_iter > 255) return fail(BPSF_EINVAL, "max_iter must be in 1..255");
+  if (p->k < 0 || p->k > 16) return fail(BPSF_EINVAL, "k must be in 0..16");
+  if (p->k > 0 && (p->cand_max_iter < 1 || p->cand_max_iter >= (1 << KEY_ITER_BITS)))
+    return fail(BPSF_EINVAL, "cand_max_iter must be in 1..4095");
+  if (p->cand_mode != BPSF_TRIALS_ALL_SUBSETS && p->cand_mode != BPSF_TRIALS_WEIGHT_LE)
+    return fail(BPSF_EINVAL, "unknown cand_mode");
+  if (p->k > 0 && p->cand_mode == BPSF_TRIALS_WEIGHT_LE && (p->w_max < 1 || p->w_max > p->k))
+    return fail(BPSF_EINVAL, "w_max must be in 1..k");
+  if (p->select_mode != BPSF_SELECT_MIN_WEIGHT && p->select_mode != BPSF_SELECT_FIRST)
+    return fail(BPSF_EINVAL, "unknown select_mode");
+  if (!(p->alpha >= 0.0) || !isfinite(p->alpha)) return fail(BPSF_EINVAL, "alpha must be finite and >= 0");
+  if (p->flags & ~(BPSF_FLAG_NO_EARLY_STOP | BPSF_FLAG_FORCE_PP)) return fail(BPSF_EINVAL, "unknown flags");
+  if (p->precision != BPSF_PREC_FP32 && p->precision != BPSF_PREC_FP64) return fail(BPSF_EINVAL, "unknown precision");
+  return 0;
+}
+
+// Channel LLRs l_v = log((1 - p_v) / p_v) (Section II-B step 1), in double on
+// the host, then stored on the device in float and double.
+int update_llr(bpsf_code_s* c, const double* priors)
+{
+  if (!priors) return fail(BPSF_EINVAL, "priors is NULL");
+  if (!c->priors.empty() && memcmp(c->priors.data(), priors, sizeof(double) * (size_t)c->N) == 0) return 0;
+  std::vector<double> l64((size_t)c->N);
+  std::vector<float> l32((size_t)c->N);
+  for (int v = 0; v < c->N; ++v) {
+    const double p = priors[v];
+    if (!(p > 0.0 && p < 1.0)) return fail(BPSF_EINVAL, "priors[%d] = %g is not in (0, 1)", v, p);
+    l64[v] = log((1.0 - p) / p);
+    l32[v] = (float)l64[v];
+  }
+  if (c->llr64.ensure(sizeof(double) * (size_t)c->N) || c->llr32.ensure(sizeof(float) * (size_t)c->N))
+    return fail(BPSF_ENOMEM, "LLR buffers");
+  HIP_OK(hipMemcpy(c->llr64.p, l64.data(), sizeof(double) * (size_t)c->N, hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(c->llr32.p, l32.data(), sizeof(float) * (size_t)c->N, hipMemcpyHostToDevice));
+  c->priors.assign(priors, priors + c->N);
+  return 0;
+}
+
+int update_masks(bpsf_code_s* c, const bpsf_params* p)
+{
+  const int wm = p->cand_mode == BPSF_TRIALS_WEIGHT_LE ? p->w_max : 0;
+  if (c->masks_k == p->k && c->masks_mode == p->cand_mode && c->masks_wmax == wm) return 0;
+  std::vector<uint32_t> m = trial_masks(p->k, p->cand_mode, wm);
+  c->n_trials = (int)m.size();
+  if (!m.empty()) {
+    if (c->masks.ensure(sizeof(uint32_t) * m.size())) return fail(BPSF_ENOMEM, "trial mask table");
+    HIP_OK(hipMemcpy(c->masks.p, m.data(), sizeof(uint32_t) * m.size(), hipMemcpyHostToDevice));
+  }
+  c->masks_k = p->k;
+  c->masks_mode = p->cand_mode;
+  c->masks_wmax = wm;
+  return 0;
+}
+
+struct Plan {
+  TileDesc tile;
+  Args args;
+  int grid[3];
+};
+
+int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
+{
+  if (pick_tile(c, &pl->tile)) return fail(BPSF_ENOTSUP, "no kernel tile for this code");
+  const TileDesc& t = pl->tile;
+  const int G = 64 / t.D;
+  Args& a = pl->args;
+  memset(&a, 0, sizeof a);
+  a.M = c->M;
+  a.N = c->N;
+  a.MS = slot_stride(G, t.IC);
+  a.CI = t.D * a.MS;
+  a.var_chk = static_cast<const uint16_t*>(c->var_chk.p);
+  a.var_pos = static_cast<const uint8_t*>(c->var_pos.p);
+  a.ell_col = static_cast<const int32_t*>(c->ell_col.p);
+  a.llr = p->precision == BPSF_PREC_FP64 ? c->llr64.p : c->llr32.p;
+  a.shots = shots;
+  a.max_iter = p->max_iter;
+  a.cand_max_iter = p->k > 0 ? p->cand_max_iter : 1;
+  a.k = p->k;
+  a.n_trials = c->n_trials;
+  a.select_first = p->select_mode == BPSF_SELECT_FIRST;
+  a.flags = p->flags;
+  a.alpha = p->alpha;
+  a.trial_masks = static_cast<const uint32_t*>(c->masks.p);
+  a.rec_stride = REC_HDR + 16 + G;
+  a.chunk = 2 * t.D;
+  // scratch: one record and key per shot at most
+  const int64_t cap = shots > 0 ? shots : 1;
+  if (c->records.ensure(sizeof(int32_t) * (size_t)a.rec_stride * (size_t)cap) ||
+      c->keys.ensure(sizeof(unsigned long long) * (size_t)cap) ||
+      c->counters.ensure(sizeof(unsigned long long) * CNT_WORDS))
+    return fail(BPSF_ENOMEM, "scratch for %lld shots", (long long)shots);
+  a.records = static_cast<int32_t*>(c->records.p);
+  a.rec_cap = cap;
+  a.keys = static_cast<unsigned long long*>(c->keys.p);
+  a.counters = static_cast<unsigned long long*>(c->counters.p);
+  const bool fp64 = p->precision == BPSF_PREC_FP64;
+  for (int mode = 0; mode < 3; ++mode) {
+    int per_cu = 0;
+    if (tile_dispatch(1, t, fp64, mode, false, a, 0, nullptr, &per_cu) || per_cu < 1)
+      return fail(BPSF_EDEVICE, "occupancy query failed for mode %d", mode);
+    pl->grid[mode] = per_cu * c->cus;
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bpsf_last_error(void) { return g_err.c_str(); }
+
+int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, int32_t N, bpsf_code* out)
+{
+  if (!out) return fail(BPSF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!row_ptr || M < 1 || N < 1) return fail(BPSF_EINVAL, "need M >= 1, N >= 1 and row_ptr");
+  if (row_ptr[0] != 0) return fail(BPSF_EINVAL, "row_ptr[0] must be 0");
+  for (int c = 0; c < M; ++c)
+    if (row_ptr[c + 1] < row_ptr[c]) return fail(BPSF_EINVAL, "row_ptr must be non-decreasing");
+  const int E = row_ptr[M];
+  if (E > 0 && !col_idx) return fail(BPSF_EINVAL, "col_idx is NULL");
+  std::vector<int> colw((size_t)N, 0);
+  int W = -1;
+  for (int c = 0; c < M; ++c) {
+    const int w = row_ptr[c + 1] - row_ptr[c];
+    if (W < 0) W = w;
+    if (w != W) return fail(BPSF_ENOTSUP, "rows of unequal weight are not supported");
+    for (int e = row_ptr[c]; e < row_ptr[c + 1]; ++e) {
+      const int v = col_idx[e];
+      if (v < 0 || v >= N) return fail(BPSF_EINVAL, "col_idx[%d] = %d out of range", e, v);
+      if (e > row_ptr[c] && v <= col_idx[e - 1]) return fail(BPSF_EINVAL, "row %d: columns must ascend", c);
+      ++colw[v];
+    }
+  }
+  const int DV = colw[0];
+  for (int v = 0; v < N; ++v)
+    if (colw[v] != DV) return fail(BPSF_ENOTSUP, "columns of unequal weight are not supported");
+  if (M > 65535) return fail(BPSF_ENOTSUP, "too many checks");
+
+  bpsf_code_s* c = new (std::nothrow) bpsf_code_s;
+  if (!c) return fail(BPSF_ENOMEM, "handle");
+  c->M = M;
+  c->N = N;
+  c->E = E;
+  c->W = W;
+  c->DV = DV;
+  TileDesc t;
+  if (pick_tile(c, &t)) { delete c; return fail(BPSF_ENOTSUP, "no kernel tile for M=%d N=%d W=%d DV=%d", M, N, W, DV); }
+
+  // checks of every bit in ascending order, and the bit's position in each row
+  std::vector<uint16_t> vchk((size_t)N * DV);
+  std::vector<uint8_t> vpos((size_t)N * DV);
+  std::vector<int32_t> ell((size_t)M * W, -1);
+  std::vector<int> fill((size_t)N, 0);
+  for (int r = 0; r < M; ++r)
+    for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+      const int v = col_idx[e];
+      const int j = e - row_ptr[r];
+      vchk[(size_t)v * DV + fill[v]] = (uint16_t)r;
+      vpos[(size_t)v * DV + fill[v]] = (uint8_t)j;
+      ++fill[v];
+      ell[(size_t)r * W + j] = v;
+    }
+  int rc = 0;
+  if (hipGetDevice(&c->device) != hipSuccess) rc = fail(BPSF_EDEVICE, "hipGetDevice");
+  hipDeviceProp_t prop;
+  if (!rc && hipGetDeviceProperties(&prop, c->device) != hipSuccess) rc = fail(BPSF_EDEVICE, "hipGetDeviceProperties");
+  if (!rc) {
+    c->cus = prop.multiProcessorCount;
+    if (c->var_chk.ensure(vchk.size() * 2) || c->var_pos.ensure(vpos.size()) || c->ell_col.ensure(ell.size() * 4))
+      rc = fail(BPSF_ENOMEM, "code tables");
+  }
+  if (!rc && (hipMemcpy(c->var_chk.p, vchk.data(), vchk.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+              hipMemcpy(c->var_pos.p, vpos.data(), vpos.size(), hipMemcpyHostToDevice) != hipSuccess ||
+              hipMemcpy(c->ell_col.p, ell.data(), ell.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
+    rc = fail(BPSF_EDEVICE, "uploading code tables");
+  if (rc) { delete c; return rc; }
+  *out = c;
+  return 0;
+}
+
+void bpsf_free_code(bpsf_code code)
+{
+  if (!code) return;
+  (void)hipDeviceSynchronize();
+  delete code;
+}
+
+int bpsf_code_info(bpsf_code c, int32_t* M, int32_t* N, int32_t* edges, int32_t* rw, int32_t* cw)
+{
+  if (!c) return fail(BPSF_EINVAL, "code is NULL");
+  if (M) *M = c->M;
+  if (N) *N = c->N;
+  if (edges) *edges = c->E;
+  if (rw) *rw = c->W;
+  if (cw) *cw = c->DV;
+  return 0;
+}
+
+int bpsf_decode(bpsf_code c, const uint8_t* syndromes, const double* priors, int64_t shots,
+                const bpsf_params* p, uint8_t* corrections, uint8_t* converged, int32_t* iterations,
+                void* stream)
+{
+  if (!c) return fail(BPSF_EINVAL, "code is NULL");
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (shots < 0) return fail(BPSF_EINVAL, "shots < 0");
+  if (shots > 0x7fffffffLL) return fail(BPSF_EINVAL, "at most 2^31-1 shots per call");
+  if (shots > 0 && (!syndromes || !corrections || !converged || !iterations))
+    return fail(BPSF_EINVAL, "NULL buffer");
+  std::lock_guard<std::mutex> lk(c->mu);
+  if ((rc = update_llr(c, priors))) return rc;
+  if (shots == 0) return 0;
+  if ((rc = update_masks(c, p))) return rc;
+  Plan pl;
+  if ((rc = make_plan(c, p, shots, &pl))) return rc;
+  Args& a = pl.args;
+  a.syndromes = syndromes;
+  a.corrections = corrections;
+  a.converged = converged;
+  a.iterations = iterations;
+  const bool fp64 = p->precision == BPSF_PREC_FP64;
+  if (reset_counters(a.counters, stream)) return fail(BPSF_EDEVICE, "counter reset launch");
+  if (tile_dispatch(0, pl.tile, fp64, MODE_MAIN, false, a, pl.grid[MODE_MAIN], stream, nullptr))
+    return fail(BPSF_EDEVICE, "first-BP launch failed");
+  if (p->k > 0) {
+    if (tile_dispatch(0, pl.tile, fp64, MODE_CAND, false, a, pl.grid[MODE_CAND], stream, nullptr))
+      return fail(BPSF_EDEVICE, "trial launch failed");
+    if (tile_dispatch(0, pl.tile, fp64, MODE_EMIT, false, a, pl.grid[MODE_EMIT], stream, nullptr))
+      return fail(BPSF_EDEVICE, "re-run launch failed");
+  }
+  return 0;
+}
+
+int bpsf_last_stats(bpsf_code c, void* stream, bpsf_stats* out)
+{
+  if (!c || !out) return fail(BPSF_EINVAL, "NULL argument");
+  memset(out, 0, sizeof *out);
+  if (!c->counters.p) return 0;
+  unsigned long long h[CNT_WORDS];
+  HIP_OK(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  HIP_OK(hipMemcpy(h, c->counters.p, sizeof h, hipMemcpyDeviceToHost));
+  out->main_iterations = (int64_t)h[ST_MAIN_ITERS];
+  out->trial_iterations = (int64_t)h[ST_CAND_ITERS];
+  out->rerun_iterations = (int64_t)h[ST_EMIT_ITERS];
+  out->failed_shots = (int64_t)h[CNT_FAILED];
+  out->converged_trials = (int64_t)h[ST_CAND_CONV];
+  out->errors = (int64_t)h[ST_ERRORS];
+  return 0;
+}
+
+int64_t bpsf_num_trials(const bpsf_params* p, uint32_t* masks_out, int64_t cap)
+{
+  int rc = check_params(p);
+  if (rc) return rc;
+  const std::vector<uint32_t> m = trial_masks(p->k, p->cand_mode, p->w_max);
+  if (masks_out)
+    for (int64_t i = 0; i < (int64_t)m.size() && i < cap; ++i) masks_out[i] = m[(size_t)i];
+  return (int64_t)m.size();
+}
+
+int bpsf_bp_trace(bpsf_code c, const uint8_t* syndrome, const double* priors, const bpsf_params* p,
+                  void* lout_trace, void* c2v_trace, uint8_t* hard_out, int32_t* iters_out, uint8_t* conv_out)
+{
+  if (!c || !syndrome || !hard_out || !iters_out || !conv_out) return fail(BPSF_EINVAL, "NULL argument");
+  int rc = check_params(p);
+  if (rc) return rc;
+  bpsf_params q = *p;
+  q.k = 0;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if ((rc = update_llr(c, priors))) return rc;
+  Plan pl;
+  if ((rc = make_plan(c, &q, 1, &pl))) return rc;
+  const size_t rb = q.precision == BPSF_PREC_FP64 ? 8 : 4;
+  const size_t nl = rb * (size_t)q.max_iter * (size_t)c->N;
+  const size_t nc = rb * (size_t)q.max_iter * (size_t)c->M * (size_t)c->W;
+  DevBuf dsyn, dcorr, dconv, dit, dl, dc;
+  if (dsyn.ensure(c->M) || dcorr.ensure(c->N) || dconv.ensure(1) || dit.ensure(4) || dl.ensure(nl) || dc.ensure(nc))
+    return fail(BPSF_ENOMEM, "trace buffers");
+  HIP_OK(hipMemcpy(dsyn.p, syndrome, c->M, hipMemcpyHostToDevice));
+  HIP_OK(hipMemset(dl.p, 0, nl));
+  HIP_OK(hipMemset(dc.p, 0, nc));
+  Args& a = pl.args;
+  a.syndromes = static_cast<const uint8_t*>(dsyn.p);
+  a.corrections = static_cast<uint8_t*>(dcorr.p);
+  a.converged = static_cast<uint8_t*>(dconv.p);
+  a.iterations = static_cast<int32_t*>(dit.p);
+  a.trace_lout = dl.p;
+  a.trace_c2v = dc.p;
+  if (reset_counters(a.counters, nullptr)) return fail(BPSF_EDEVICE, "counter reset launch");
+  if (tile_dispatch(0, pl.tile, q.precision == BPSF_PREC_FP64, MODE_MAIN, true, a, 1, nullptr, nullptr))
+    return fail(BPSF_EDEVICE, "trace launch failed");
+  HIP_OK(hipDeviceSynchronize());
+  HIP_OK(hipMemcpy(hard_out, dcorr.p, c->N, hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(conv_out, dconv.p, 1, hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(iters_out, dit.p, 4, hipMemcpyDeviceToHost));
+  if (lout_trace) HIP_OK(hipMemcpy(lout_trace, dl.p, nl, hipMemcpyDeviceToHost));
+  if (c2v_trace) HIP_OK(hipMemcpy(c2v_trace, dc.p, nc, hipMemcpyDeviceToHost));
+  return 0;
+}
+
+}  // extern "C"

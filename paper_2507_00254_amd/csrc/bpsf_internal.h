@@ -1,0 +1,74 @@
+// Internal definitions shared by the BP-SF device kernels and the host runtime.
+// Not part of the public ABI (that is include/bpsf.h).
+#pragma once
+
+#include <stdint.h>
+
+namespace bpsf {
+
+// Decode phases of one bpsf_decode call, each a persistent launch:
+//   MAIN  - BP with oscillation counting on every shot (Algorithm 1, first BP);
+//           shots that fail get a record with Phi = top(flip_count, k);
+//   CAND  - one short BP per (failed shot, trial vector) on s' = s + t H^T; a
+//           successful trial posts its key (weight, trial index, iterations);
+//   EMIT  - re-runs each failed shot's winning trial and writes its undone
+//           correction (the run is deterministic, so it reproduces the winner).
+enum Mode : int { MODE_MAIN = 0, MODE_CAND = 1, MODE_EMIT = 2 };
+
+// Record layout for a shot whose first BP failed (int32 words).
+enum : int { REC_SHOT = 0, REC_MAIN_ITERS = 1, REC_MAIN_CONV = 2, REC_HDR = 4 };
+
+// Counters and statistics (uint64 words in the scratch block).
+enum : int {
+  CNT_MAIN_NEXT = 0,    // next shot to take in MAIN
+  CNT_FAILED = 1,       // records written by MAIN
+  CNT_CAND_NEXT = 2,    // next (record, trial) task in CAND
+  CNT_EMIT_NEXT = 3,    // next record in EMIT
+  ST_MAIN_ITERS = 4,    // sum of first-BP iterations
+  ST_CAND_ITERS = 5,    // sum of trial-BP iterations
+  ST_EMIT_ITERS = 6,    // sum of re-run iterations
+  ST_CAND_CONV = 7,     // trials that converged
+  ST_ERRORS = 8,        // a re-run that did not reproduce its winner (must stay 0)
+  ST_WAVES = 9,         // waves that ran to completion
+  CNT_WORDS = 16
+};
+
+static constexpr uint64_t KEY_NONE = ~0ull;
+static constexpr int KEY_ITER_BITS = 12;     // trial iterations (< 4096)
+static constexpr int KEY_TRIAL_BITS = 32;    // trial index
+static constexpr int KEY_WEIGHT_SHIFT = KEY_ITER_BITS + KEY_TRIAL_BITS;
+
+struct Args {
+  // code (device, immutable)
+  int M, N;               // checks, bits
+  int MS;                 // slot stride in the message array (>= G * IC)
+  int CI;                 // D * MS: message-array stride between edge positions
+  const uint16_t* var_chk;   // [N][DV] checks of each bit, ascending
+  const uint8_t* var_pos;    // [N][DV] position of the bit inside each check's row
+  const int32_t* ell_col;    // [M][W] bits of each check, row order (ELL, -1 padded)
+  const void* llr;           // [N] channel LLR (float or double)
+  // problem (device)
+  const uint8_t* syndromes;  // [shots][M]
+  int64_t shots;
+  uint8_t* corrections;      // [shots][N]
+  uint8_t* converged;        // [shots]
+  int32_t* iterations;       // [shots]
+  // parameters
+  int max_iter, cand_max_iter, k, n_trials, select_first, flags;
+  double alpha;              // > 0 fixed; 0 adaptive 1 - 2^-i
+  const uint32_t* trial_masks;  // [n_trials]
+  // scratch (device)
+  int32_t* records;          // [cap][rec_stride]
+  int rec_stride;
+  int64_t rec_cap;
+  unsigned long long* keys;  // [cap]
+  unsigned long long* counters;  // [CNT_WORDS]
+  // per-iteration records of slot 0 (debug entry point only)
+  void* trace_lout;          // [max_iter][N] Real
+  void* trace_c2v;           // [max_iter][M*W] Real (row-major edge order)
+  int chunk;                 // tasks reserved per counter update
+};
+
+enum : int { FLAG_NO_EARLY_STOP = 1, FLAG_FORCE_PP = 2 };
+
+}  // namespace bpsf
