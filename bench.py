@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the BP-SF decoder on one MI355X.
+
+Workload: the [[144,12,12]] bivariate-bicycle code (H_X, 72 x 144, 432 edges),
+code-capacity i.i.d. bit flips with p = 0.03, 10^6 seeded shots resident in
+HBM; min-sum with alpha = 0.625, 100 first-BP iterations, |Phi| = 6 giving 64
+trial vectors of 20-iteration BP, lightest successful trial kept, float
+messages. One step decodes all 10^6 shots (first BP, trial BPs, winner
+re-runs). Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+EDGE_BYTES = 16          # one float v2c and one float c2v per edge, each written once and read once
+LDS_PEAK_GBS = 256 * 128 * 2.4   # 256 CUs x 128 B/clk x 2.4 GHz = 78,643 GB/s
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4 / 1000   # 32-bit VALU lane-ops: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+KERNEL_SOURCES = ("paper_2507_00254_amd/csrc/bpsf_kernels.hip", "paper_2507_00254_amd/csrc/bpsf_tiles.h",
+                  "paper_2507_00254_amd/csrc/bpsf_internal.h")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(phase: str, launches_bytes_key: str = "hbm_bytes_per_dispatch"):
+    """HBM bytes per launch from a committed counter summary, when it was taken
+    on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_bb144_p003.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_src_sha") != kernel_hash():
+        return None
+    return rec.get("phases", {}).get(phase, {}).get(launches_bytes_key)
+
+
+def cpu_baseline(h, syn, p, prm, seconds: float):
+    from oracle.oracle import OracleLib
+    threads = min(os.cpu_count() or 1, 16)
+    O = OracleLib()
+    done, t0 = 0, time.perf_counter()
+    chunk = 20000
+    while time.perf_counter() - t0 < seconds and done < len(syn):
+        O.bpsf_batch(h, syn[done:done + chunk], p, prm, prec="f64", threads=threads)
+        done += min(chunk, len(syn) - done)
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "shots/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {done} shots of the same workload, double-precision oracle, "
+                      f"{threads} threads, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--shots", type=int, default=1_000_000)
+    ap.add_argument("--p", type=float, default=0.03)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency-calls", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(shots shard independently across GPUs; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2507_00254_amd import bpsf as B
+    from workloads import codes, shots
+
+    code = codes.bb144()
+    p = args.p
+    n = args.shots
+    key = shots.stream_key(shots.MASTER_SEED, 2, code.n, int(round(p * 100000)))
+    _, syn = shots.make_shots(code.hx, p, n, key)
+    pri = np.full(code.n, p)
+    prm = B.make_params(max_iter=100, cand_max_iter=20, k=6, alpha=0.625, precision=B.PREC_FP32)
+
+    torch.cuda.set_device(0)
+    handle = B.bpsf_load_code(code.hx)
+    edges = B.bpsf_code_info(handle)["edges"]
+    s = torch.from_numpy(syn).cuda()
+    corr = torch.empty((n, code.n), dtype=torch.uint8, device="cuda")
+    conv = torch.empty((n,), dtype=torch.uint8, device="cuda")
+    it = torch.empty((n,), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        B.bpsf_decode(handle, s, pri, prm, corr, conv, it, stream)
+    torch.cuda.synchronize()
+
+    B.bpsf_set_timing(handle, True)
+    phase_ms = {"main": 0.0, "trials": 0.0, "rerun": 0.0}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        B.bpsf_decode(handle, s, pri, prm, corr, conv, it, stream)
+        tm = B.bpsf_last_timing(handle)          # waits for this step's events
+        for k2 in phase_ms:
+            phase_ms[k2] += tm[k2]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    B.bpsf_set_timing(handle, False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    st = B.bpsf_last_stats(handle, stream)
+    conv_rate = float(conv.float().mean().item())
+
+    # dominant kernel: the phase with the largest mean duration
+    iters = {"main": st["main_iterations"], "trials": st["trial_iterations"], "rerun": st["rerun_iterations"]}
+    avg_ms = {k2: v / args.steps for k2, v in phase_ms.items()}
+    dom = max(avg_ms, key=avg_ms.get)
+    alg_bytes = EDGE_BYTES * edges * iters[dom]
+    achieved = alg_bytes / (avg_ms[dom] * 1e-3) / 1e9
+    traffic = traffic_from_profile(dom)
+
+    # request latency: 256-shot batches decoded one at a time on an idle GPU
+    lat = []
+    if args.latency_calls > 0:
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        sub = s[:256]
+        o1, o2, o3 = corr[:256], conv[:256], it[:256]
+        for i in range(args.latency_calls):
+            off = (i * 256) % (n - 256)
+            sub = s[off:off + 256]
+            ev0.record(stream)
+            B.bpsf_decode(handle, sub, pri, prm, o1, o2, o3, stream)
+            ev1.record(stream)
+            ev1.synchronize()
+            lat.append(ev0.elapsed_time(ev1) * 1e3)
+    lat = np.array(lat) if lat else np.array([np.nan])
+
+    out = {
+        "metric": "decoded shots/s at [[144,12,12]] p=0.03 (BP-SF); p99 decode latency (us)",
+        "value": n / (ms_per_step * 1e-3),
+        "unit": "shots/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded i.i.d. bit flips, s = H_X e)",
+        "config": {"workload": "bb144_codecap_p0.03_1e6", "code": "[[144,12,12]] H_X 72x144", "shots": n, "p": p,
+                   "max_iter": 100, "k": 6, "trials": 64, "trial_iter": 20, "alpha": 0.625},
+        "p99_latency_us": float(np.percentile(lat, 99)),
+        "latency": {"request_shots": 256, "calls": int(len(lat)), "p50_us": float(np.percentile(lat, 50)),
+                    "p99_us": float(np.percentile(lat, 99)), "max_us": float(np.max(lat))},
+        "phases_ms": avg_ms,
+        "work": {"edges": edges, **iters, "failed_shots": st["failed_shots"], "converged_rate": conv_rate},
+        "roofline": {"bound": "lds", "kernel": dom, "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / LDS_PEAK_GBS, "traffic": traffic,
+                     "per_unit": f"{EDGE_BYTES} B per edge-iteration x {edges} edges x {iters[dom]} iterations"},
+        "kernel_src_sha": kernel_hash(),
+    }
+    total_edge_iters = edges * sum(iters.values())
+    out["whole_call"] = {"edge_iterations_per_s": total_edge_iters / (ms_per_step * 1e-3),
+                         "lds_equiv_GBps": EDGE_BYTES * total_edge_iters / (ms_per_step * 1e-3) / 1e9}
+    if not args.no_cpu_baseline:
+        from oracle.oracle import Params
+        oprm = Params(max_iter=100, cand_max_iter=20, k=6, alpha=0.625)
+        out["cpu_baseline"] = cpu_baseline(code.hx, syn, p, oprm, args.cpu_seconds)
+    B.bpsf_free_code(handle)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

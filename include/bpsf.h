@@ -140,6 +140,16 @@ int bpsf_bp_trace(bpsf_code code, const uint8_t* syndrome, const double* priors,
  */
 int64_t bpsf_num_trials(const bpsf_params* params, uint32_t* masks_out, int64_t cap);
 
+/*
+ * Per-phase timing. With enable != 0, every later bpsf_decode on this handle
+ * records HIP events on its stream around each of its kernels (the events are
+ * created here, once). bpsf_last_timing waits for the last decode's stream and
+ * writes ms_out[4] = {whole call, first BP, trial BPs, winner re-runs}
+ * (host out; phases that did not run report 0).
+ */
+int bpsf_set_timing(bpsf_code code, int enable);
+int bpsf_last_timing(bpsf_code code, float* ms_out);
+
 /* Shape of a loaded code: M, N, edges, row weight, column weight (host outs, any may be NULL). */
 int bpsf_code_info(bpsf_code code, int32_t* M, int32_t* N, int32_t* edges, int32_t* row_weight,
                    int32_t* col_weight);

@@ -56,6 +56,8 @@ def _load():
                                   P(i32), P(C.c_uint8)]
     lib.bpsf_num_trials.argtypes = [P(bpsf_params), P(C.c_uint32), i64]
     lib.bpsf_num_trials.restype = i64
+    lib.bpsf_set_timing.argtypes = [vp, C.c_int]
+    lib.bpsf_last_timing.argtypes = [vp, P(C.c_float)]
     lib.bpsf_code_info.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(i32)]
     lib.bpsf_last_error.argtypes = []
     lib.bpsf_last_error.restype = C.c_char_p
@@ -137,6 +139,17 @@ def bpsf_last_stats(handle, stream=None) -> dict:
     st = bpsf_stats()
     _check(LIB.bpsf_last_stats(C.c_void_p(handle), _stream_ptr(stream), C.byref(st)))
     return {f: getattr(st, f) for f, _ in bpsf_stats._fields_}
+
+
+def bpsf_set_timing(handle, enable: bool) -> None:
+    _check(LIB.bpsf_set_timing(C.c_void_p(handle), int(bool(enable))))
+
+
+def bpsf_last_timing(handle) -> dict:
+    """Durations (ms) of the last timed decode: whole call and each phase."""
+    ms = (C.c_float * 4)()
+    _check(LIB.bpsf_last_timing(C.c_void_p(handle), ms))
+    return {"total": ms[0], "main": ms[1], "trials": ms[2], "rerun": ms[3]}
 
 
 def bpsf_code_info(handle) -> dict:

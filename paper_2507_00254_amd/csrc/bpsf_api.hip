@@ -71,13 +71,25 @@ struct bpsf_code_s {
   DevBuf var_chk, var_pos, ell_col;
   // channel LLR cache
   std::vector<double> priors;
+  bool uniform = false;       // every prior equal (the LLR is then a kernel scalar)
+  double llr_uniform = 0.0;
   DevBuf llr32, llr64;
   // trial masks cache
   int masks_k = -1, masks_mode = -1, masks_wmax = -1, n_trials = 0;
   DevBuf masks;
   // scratch
   DevBuf records, keys, counters;
+  // optional per-phase timing: events[i] marks the boundary before phase i
+  bool timing = false;
+  bool timed_last = false;
+  int timed_phases = 0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::mutex mu;
+  ~bpsf_code_s()
+  {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -166,6 +178,10 @@ int update_llr(bpsf_code_s* c, const double* priors)
   HIP_OK(hipMemcpy(c->llr64.p, l64.data(), sizeof(double) * (size_t)c->N, hipMemcpyHostToDevice));
   HIP_OK(hipMemcpy(c->llr32.p, l32.data(), sizeof(float) * (size_t)c->N, hipMemcpyHostToDevice));
   c->priors.assign(priors, priors + c->N);
+  c->uniform = true;
+  for (int v = 1; v < c->N; ++v)
+    if (priors[v] != priors[0]) c->uniform = false;
+  c->llr_uniform = l64[0];
   return 0;
 }
 
@@ -194,18 +210,18 @@ struct Plan {
 int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
 {
   if (pick_tile(c, &pl->tile)) return fail(BPSF_ENOTSUP, "no kernel tile for this code");
+  if (p->k > c->N) return fail(BPSF_EINVAL, "k = %d exceeds the %d bits of the code", p->k, c->N);
   const TileDesc& t = pl->tile;
   const int G = 64 / t.D;
   Args& a = pl->args;
   memset(&a, 0, sizeof a);
   a.M = c->M;
   a.N = c->N;
-  a.MS = slot_stride(G, t.IC);
-  a.CI = t.D * a.MS;
   a.var_chk = static_cast<const uint16_t*>(c->var_chk.p);
   a.var_pos = static_cast<const uint8_t*>(c->var_pos.p);
   a.ell_col = static_cast<const int32_t*>(c->ell_col.p);
   a.llr = p->precision == BPSF_PREC_FP64 ? c->llr64.p : c->llr32.p;
+  a.llr_uniform = c->llr_uniform;
   a.shots = shots;
   a.max_iter = p->max_iter;
   a.cand_max_iter = p->k > 0 ? p->cand_max_iter : 1;
@@ -215,7 +231,9 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
   a.flags = p->flags;
   a.alpha = p->alpha;
   a.trial_masks = static_cast<const uint32_t*>(c->masks.p);
-  a.rec_stride = REC_HDR + 16 + G;
+  // record: header, s bits per lane, every Phi column's share per lane, Phi
+  const int kk = p->k > 0 ? p->k : 1;
+  a.rec_stride = REC_HDR + G * (kk + 1) + kk;
   a.chunk = 2 * t.D;
   // scratch: one record and key per shot at most
   const int64_t cap = shots > 0 ? shots : 1;
@@ -230,7 +248,7 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
   const bool fp64 = p->precision == BPSF_PREC_FP64;
   for (int mode = 0; mode < 3; ++mode) {
     int per_cu = 0;
-    if (tile_dispatch(1, t, fp64, mode, false, a, 0, nullptr, &per_cu) || per_cu < 1)
+    if (tile_dispatch(1, t, fp64, c->uniform, mode, false, a, 0, nullptr, &per_cu) || per_cu < 1)
       return fail(BPSF_EDEVICE, "occupancy query failed for mode %d", mode);
     pl->grid[mode] = per_cu * c->cus;
   }
@@ -354,15 +372,45 @@ int bpsf_decode(bpsf_code c, const uint8_t* syndromes, const double* priors, int
   a.converged = converged;
   a.iterations = iterations;
   const bool fp64 = p->precision == BPSF_PREC_FP64;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (reset_counters(a.counters, stream)) return fail(BPSF_EDEVICE, "counter reset launch");
-  if (tile_dispatch(0, pl.tile, fp64, MODE_MAIN, false, a, pl.grid[MODE_MAIN], stream, nullptr))
+  if (c->timing) HIP_OK(hipEventRecord(c->ev[0], st));
+  if (tile_dispatch(0, pl.tile, fp64, c->uniform, MODE_MAIN, false, a, pl.grid[MODE_MAIN], stream, nullptr))
     return fail(BPSF_EDEVICE, "first-BP launch failed");
+  if (c->timing) HIP_OK(hipEventRecord(c->ev[1], st));
   if (p->k > 0) {
-    if (tile_dispatch(0, pl.tile, fp64, MODE_CAND, false, a, pl.grid[MODE_CAND], stream, nullptr))
+    if (tile_dispatch(0, pl.tile, fp64, c->uniform, MODE_CAND, false, a, pl.grid[MODE_CAND], stream, nullptr))
       return fail(BPSF_EDEVICE, "trial launch failed");
-    if (tile_dispatch(0, pl.tile, fp64, MODE_EMIT, false, a, pl.grid[MODE_EMIT], stream, nullptr))
+    if (c->timing) HIP_OK(hipEventRecord(c->ev[2], st));
+    if (tile_dispatch(0, pl.tile, fp64, c->uniform, MODE_EMIT, false, a, pl.grid[MODE_EMIT], stream, nullptr))
       return fail(BPSF_EDEVICE, "re-run launch failed");
+    if (c->timing) HIP_OK(hipEventRecord(c->ev[3], st));
   }
+  c->timed_last = c->timing;
+  c->timed_phases = p->k > 0 ? 3 : 1;
+  return 0;
+}
+
+int bpsf_set_timing(bpsf_code c, int enable)
+{
+  if (!c) return fail(BPSF_EINVAL, "code is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (enable && !c->ev[0])
+    for (auto& e : c->ev) HIP_OK(hipEventCreate(&e));
+  c->timing = enable != 0;
+  return 0;
+}
+
+int bpsf_last_timing(bpsf_code c, float* ms)
+{
+  if (!c || !ms) return fail(BPSF_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(c->mu);
+  for (int i = 0; i < 4; ++i) ms[i] = 0.f;
+  if (!c->timed_last) return fail(BPSF_EINVAL, "the last decode on this handle was not timed");
+  const int last = c->timed_phases;
+  HIP_OK(hipEventSynchronize(c->ev[last]));
+  HIP_OK(hipEventElapsedTime(&ms[0], c->ev[0], c->ev[last]));
+  for (int i = 0; i < last; ++i) HIP_OK(hipEventElapsedTime(&ms[i + 1], c->ev[i], c->ev[i + 1]));
   return 0;
 }
 
@@ -422,7 +470,7 @@ int bpsf_bp_trace(bpsf_code c, const uint8_t* syndrome, const double* priors, co
   a.trace_lout = dl.p;
   a.trace_c2v = dc.p;
   if (reset_counters(a.counters, nullptr)) return fail(BPSF_EDEVICE, "counter reset launch");
-  if (tile_dispatch(0, pl.tile, q.precision == BPSF_PREC_FP64, MODE_MAIN, true, a, 1, nullptr, nullptr))
+  if (tile_dispatch(0, pl.tile, q.precision == BPSF_PREC_FP64, c->uniform, MODE_MAIN, true, a, 1, nullptr, nullptr))
     return fail(BPSF_EDEVICE, "trace launch failed");
   HIP_OK(hipDeviceSynchronize());
   HIP_OK(hipMemcpy(hard_out, dcorr.p, c->N, hipMemcpyDeviceToHost));

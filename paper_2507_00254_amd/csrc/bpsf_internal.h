@@ -41,12 +41,11 @@ static constexpr int KEY_WEIGHT_SHIFT = KEY_ITER_BITS + KEY_TRIAL_BITS;
 struct Args {
   // code (device, immutable)
   int M, N;               // checks, bits
-  int MS;                 // slot stride in the message array (>= G * IC)
-  int CI;                 // D * MS: message-array stride between edge positions
   const uint16_t* var_chk;   // [N][DV] checks of each bit, ascending
   const uint8_t* var_pos;    // [N][DV] position of the bit inside each check's row
   const int32_t* ell_col;    // [M][W] bits of each check, row order (ELL, -1 padded)
   const void* llr;           // [N] channel LLR (float or double)
+  double llr_uniform;        // the common channel LLR when every prior is equal
   // problem (device)
   const uint8_t* syndromes;  // [shots][M]
   int64_t shots;

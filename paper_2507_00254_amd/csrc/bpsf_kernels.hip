@@ -17,12 +17,17 @@
 //     stride MS per slot and CI = D*MS per position, so check-phase accesses
 //     are consecutive words and bit-phase gathers are mostly consecutive on
 //     quasi-cyclic codes;
-//   * the syndrome test is incremental: a residual bitmap r = s + H e (one bit
-//     per check, laid out like the check items) is toggled only when a hard
-//     decision flips; a slot has converged when its residual bits are zero;
+//   * the syndrome test is incremental: an LDS bitmap u = H e (one bit per
+//     check, laid out like the check items) is toggled only when a hard
+//     decision flips, and a slot has converged when u equals its syndrome; a
+//     refilled slot keeps its previous hard decisions as the toggle baseline,
+//     so u never needs re-initializing;
 //   * flip counts are bit-sliced counters (8 planes) in registers;
 //   * a finished slot is refilled at once from an LDS ring of tasks whose
-//     inputs were prefetched one iteration earlier (early-exit compaction).
+//     inputs were prefetched one iteration earlier (early-exit compaction);
+//   * a failed first BP leaves a record holding, per lane, its check bits of
+//     s and, for every bit of Phi, the lane's share of that bit's column, so a
+//     trial's s' and t are a few XORs away.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -48,6 +53,11 @@ template <> struct RT<float> {
     return __builtin_amdgcn_fmed3f(a, b, c);
   }
   static __device__ __forceinline__ float from_double(double x) { return (float)x; }
+  // 1 - 2^-i: exact in float for i <= 24 and rounded to 1 beyond, as the
+  // double value converted to float would be
+  static __device__ __forceinline__ float adaptive_alpha(int i) { return 1.0f - ldexpf(1.0f, -i); }
+  // sign bit set exactly when x <= 0 (the hard decision of step 4); x is never -0 or NaN here
+  static __device__ __forceinline__ uint32_t nonpos_msb(float x) { return __float_as_uint(x) - 1u; }
   // keeps the compiler from re-associating a select with a later multiply
   static __device__ __forceinline__ void opaque(float& a) { asm volatile("" : "+v"(a)); }
 };
@@ -68,49 +78,73 @@ template <> struct RT<double> {
     return fmax(fmin(a, b), fmin(fmax(a, b), c));
   }
   static __device__ __forceinline__ double from_double(double x) { return x; }
+  static __device__ __forceinline__ double adaptive_alpha(int i) { return 1.0 - ldexp(1.0, -i); }
+  static __device__ __forceinline__ uint32_t nonpos_msb(double x) {
+    return (uint32_t)(((unsigned long long)__double_as_longlong(x) - 1ull) >> 32);
+  }
   static __device__ __forceinline__ void opaque(double& a) { asm volatile("" : "+v"(a)); }
 };
 
-__device__ __forceinline__ int bcast0(int x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ long long bcast0ll(long long x) {
   int lo = __builtin_amdgcn_readfirstlane((int)(x & 0xffffffff));
   int hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
   return ((long long)hi << 32) | (unsigned int)lo;
 }
 
+// Butterfly reductions over the G contiguous lanes of a slot. Steps inside a
+// row of 16 lanes use DPP lane permutations (no LDS traffic).
+template <int G, class Op>
+__device__ __forceinline__ uint32_t group_reduce(uint32_t x, Op op)
+{
+  if constexpr (G >= 2) x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false));  // lane ^ 1
+  if constexpr (G >= 4) x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false));  // lane ^ 2
+  if constexpr (G >= 8) x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false)); // mirror in 8
+  if constexpr (G >= 16) x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xF, 0xF, false)); // mirror in 16
+  if constexpr (G >= 32) x = op(x, (uint32_t)__shfl_xor((int)x, 16));
+  if constexpr (G >= 64) x = op(x, (uint32_t)__shfl_xor((int)x, 32));
+  return x;
+}
+
+struct OpAdd { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a + b; } };
+struct OpMax { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a > b ? a : b; } };
+
 // --------------------------------------------------------------- kernel --
 
-template <typename Real, int D, int IC, int IV, int W, int DV, int MODE, bool TRACE>
+// UL: every bit has the same channel LLR (uniform priors), held in a scalar.
+template <typename Real, int D, int IC, int IV, int W, int DV, bool UL, int MODE, bool TRACE>
 __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
 {
   using T = TileShape<D, IC, IV, W, DV>;
   using R = RT<Real>;
-  constexpr int G = T::G, LG = T::LG, RING = T::RING, PL = T::PL, META = T::META, KG = T::KG;
-  constexpr int KMAX = T::KMAX;
-  constexpr int NRESET = reset_slots<T>();   // the host keeps MS < G*IC + 32
+  constexpr int G = T::G, LG = T::LG, RING = T::RING, PL = T::PL, META = T::META;
+  constexpr int KMAX = T::KMAX, MS = T::MS, CI = T::CI, MSB = T::MSB;
+  static_assert(IC <= 16, "check items are packed into 16-bit column masks");
 
   extern __shared__ __align__(16) unsigned char smem[];
-  const LdsLayout lay = lds_layout(sizeof(Real), W, a.CI, T::RW, a.N, DV, RING, META, KMAX, G);
+  const LdsLayout lay = lds_layout(sizeof(Real), W, CI, T::RW, a.N, DV, RING, META, KMAX, G);
   Real* msg = reinterpret_cast<Real*>(smem + lay.msg);
-  uint32_t* resid = reinterpret_cast<uint32_t*>(smem + lay.resid);
+  uint32_t* uw = reinterpret_cast<uint32_t*>(smem + lay.resid);
   uint16_t* chk = reinterpret_cast<uint16_t*>(smem + lay.chk);
   int32_t* ring_meta = reinterpret_cast<int32_t*>(smem + lay.ring_meta);
-  int32_t* ring_tv = reinterpret_cast<int32_t*>(smem + lay.ring_tv);
   uint32_t* ring_syn = reinterpret_cast<uint32_t*>(smem + lay.ring_syn);
+  uint32_t* ring_tb = reinterpret_cast<uint32_t*>(smem + lay.ring_tv);
 
   const int lane = threadIdx.x;
   const int d = lane >> LG;          // slot
   const int q = lane & (G - 1);      // lane within the slot
-  const int M = a.M, N = a.N, MS = a.MS, CI = a.CI;
+  const int M = a.M, N = a.N;
   const Real* __restrict__ llr = reinterpret_cast<const Real*>(a.llr);
+  const Real Lu = R::from_double(a.llr_uniform);   // used when UL
+  const bool adaptive = !(a.alpha > 0.0);
+  const Real alpha_fixed = R::from_double(adaptive ? 1.0 : a.alpha);
 
   // ---- per-code tables into LDS ------------------------------------------
   for (int i = lane; i < N * DV; i += 64) chk[i] = a.var_chk[i];
-  for (int i = lane; i < T::RW; i += 64) resid[i] = 0u;
+  for (int i = lane; i < T::RW; i += 64) uw[i] = 0u;
 
   // ---- per-lane constants -------------------------------------------------
   // bit items: channel LLR and the byte offsets of their DV edges
-  Real Lv[IV];
+  Real Lv[UL ? 1 : IV];
   uint32_t off[IV][DV];
   uint32_t vmask = 0;
   const uint32_t sink = lay.msg + (uint32_t)sizeof(Real) * (uint32_t)(W * CI + lane);
@@ -119,7 +153,7 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
     const int v = q + G * k;
     if (v < N) {
       vmask |= 1u << k;
-      Lv[k] = llr[v];
+      if constexpr (!UL) Lv[k] = llr[v];
 #pragma unroll
       for (int j = 0; j < DV; ++j) {
         const int c = a.var_chk[v * DV + j];
@@ -127,45 +161,37 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
         off[k][j] = lay.msg + (uint32_t)sizeof(Real) * (uint32_t)(p * CI + d * MS + c);
       }
     } else {
-      Lv[k] = (Real)0;
+      if constexpr (!UL) Lv[k] = (Real)0;
 #pragma unroll
       for (int j = 0; j < DV; ++j) off[k][j] = sink;
     }
   }
-  // check items: word offsets of position 0 (positions are CI apart)
-  const int cbase = d * MS + q;
-  // valid check items (c < M)
-  uint32_t cmask = 0;
-#pragma unroll
-  for (int k = 0; k < IC; ++k)
-    if (q + G * k < M) cmask |= 1u << k;
+  if constexpr (UL) Lv[0] = Lu;
+  const int cbase = d * MS + q;      // check items: entry of position 0, item 0
 
   // message reset: a fresh decode starts from c2v = 0, i.e. v2c = L of the
-  // edge's bit; every lane covers entries i = lane + 64 r of the slot's
-  // W x MS block (r < NR), stored with the value to write
-  const int NR = (W * MS + 63) / 64;
-  uint32_t rst_off[NRESET];
-  Real rst_val[NRESET];
+  // edge's bit. Lane i covers entries c = i + 64 h (h < MSB) of every edge
+  // position of a slot; with non-uniform priors it keeps the values to write.
+  Real rst_val[UL ? 1 : W][UL ? 1 : MSB];
+  if constexpr (!UL) {
 #pragma unroll
-  for (int r = 0; r < NRESET; ++r) {
-    const int i = lane + 64 * r;
-    rst_off[r] = 0xffffffffu;
-    rst_val[r] = (Real)0;
-    if (r < NR && i < W * MS) {
-      const int j = i / MS, c = i - j * MS;
-      rst_off[r] = lay.msg + (uint32_t)sizeof(Real) * (uint32_t)(j * CI + c);
-      if (c < M) {
-        const int v = a.ell_col[c * W + j];
-        rst_val[r] = v >= 0 ? llr[v] : (Real)0;
+    for (int j = 0; j < W; ++j)
+#pragma unroll
+      for (int h = 0; h < MSB; ++h) {
+        const int c = lane + 64 * h;
+        int v = -1;
+        if (c < M) v = a.ell_col[c * W + j];
+        rst_val[j][h] = v >= 0 ? llr[v] : (Real)0;
       }
-    }
   }
 
   // ---- slot state (uniform over the G lanes of a slot) --------------------
   bool active = false;
   int iter = 0;                 // iterations done by the current decode
   uint32_t synbits = 0;         // s (or s') of my check items, bit k
-  uint32_t hb = 0, prevhb = 0;  // hard decisions of my bit items, bit k
+  uint32_t hb = 0;              // hard decisions of my bit items, bit k
+  uint32_t prevt = 0;           // hard decisions u was last toggled to
+  uint32_t prevc = 0;           // previous hard decisions of this decode (flip counting)
   uint32_t cnt[PL];             // bit-sliced flip counts of my bit items
 #pragma unroll
   for (int b = 0; b < PL; ++b) cnt[b] = 0;
@@ -189,22 +215,24 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
     next_ctr = &a.counters[CNT_EMIT_NEXT];
   }
   n_tasks = bcast0ll(n_tasks);
+  const int rstride = a.rec_stride;
 
   int head = 0, tail = 0;                 // ring positions (monotonic)
   long long cnext = 0, cend = 0;          // reserved task range
   bool exhausted = false;
   int pend_n = 0;                         // tasks whose inputs are in flight
   long long pend_base = 0;
-  // in-flight inputs of entry dd = d (lane (dd, q))
-  uint32_t pf_b[IC];
-  uint32_t pf_syn = 0;
-  int pf_shot = 0, pf_miters = 0, pf_f = 0, pf_ti = 0, pf_phi[KG];
+  // in-flight inputs of pending entry dd = d, held by lane (d, q)
+  uint32_t pf_b[IC];                      // MAIN: syndrome bytes of my checks
+  uint32_t pf_syn = 0;                    // CAND/EMIT: s bits of my checks
+  uint32_t pf_tw[KMAX];                   // CAND/EMIT: my share of every Phi column
   uint32_t pf_mask = 0;
+  int pf_shot = 0, pf_miters = 0, pf_f = 0, pf_ti = 0;
   unsigned long long pf_key = KEY_NONE;
 #pragma unroll
   for (int k = 0; k < IC; ++k) pf_b[k] = 0;
 #pragma unroll
-  for (int r = 0; r < KG; ++r) pf_phi[r] = -1;
+  for (int j = 0; j < KMAX; ++j) pf_tw[j] = 0;
 
   // Reserve up to D tasks and start loading their inputs.
   auto issue_prefetch = [&]() {
@@ -240,18 +268,16 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
         pf_key = a.keys[f];
         ti = pf_key == KEY_NONE ? 0 : (long long)((pf_key >> KEY_ITER_BITS) & 0xffffffffull);
       }
-      const int32_t* r = a.records + f * (long long)a.rec_stride;
-      pf_syn = (uint32_t)r[REC_HDR + KMAX + q];
+      const int32_t* r = a.records + f * (long long)rstride;
+      pf_syn = (uint32_t)r[REC_HDR + q];
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j)
+        if (j < a.k) pf_tw[j] = (uint32_t)r[REC_HDR + G + j * G + q];
       pf_shot = r[REC_SHOT];
       pf_miters = r[REC_MAIN_ITERS];
-#pragma unroll
-      for (int rr = 0; rr < KG; ++rr) {
-        const int j = q + G * rr;
-        pf_phi[rr] = j < a.k ? r[REC_HDR + j] : -1;
-      }
       pf_mask = a.trial_masks[ti];
       pf_ti = (int)ti;
-      pf_f = (int)f;   // records never exceed the shots of one call (int32 range, checked on the host)
+      pf_f = (int)f;   // records never exceed the shots of one call (int32, checked on the host)
     }
   };
 
@@ -277,15 +303,20 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
           ring_meta[e * META + 1] = (int32_t)(t >> 32);
         }
       } else {
-        ring_syn[e * G + q] = pf_syn;
+        // s' = s + t H^T on my checks, and t on my bits
+        uint32_t s2 = pf_syn, tb = 0;
 #pragma unroll
-        for (int rr = 0; rr < KG; ++rr) {
-          const int j = q + G * rr;
-          if (j < KMAX) ring_tv[e * KMAX + j] = (j < a.k && ((pf_mask >> j) & 1u)) ? pf_phi[rr] : -1;
+        for (int j = 0; j < KMAX; ++j) {
+          if (j < a.k && ((pf_mask >> j) & 1u)) {
+            s2 ^= pf_tw[j] & 0xffffu;
+            const uint32_t vi = pf_tw[j] >> 16;
+            if (vi) tb |= 1u << (vi - 1u);
+          }
         }
+        ring_syn[e * G + q] = s2;
+        ring_tb[e * G + q] = tb;
         if (q == 0) {
           ring_meta[e * META + 0] = pf_shot;
-          ring_meta[e * META + 1] = 0;
           ring_meta[e * META + 2] = pf_f;
           ring_meta[e * META + 3] = pf_ti;
           ring_meta[e * META + 4] = pf_miters;
@@ -304,39 +335,24 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
     const int rank = __popcll(wb & ((1ull << (d * G)) - 1ull));
     const bool take = want && rank < avail;
     const int e = (head + rank) % RING;
-    const int ntake = __popcll(wb) < avail ? __popcll(wb) : avail;
-    head += ntake;
+    const int nw = __popcll(wb);
+    head += nw < avail ? nw : avail;
     if (want) active = false;
     if (take) {
       active = true;
       iter = 0;
-      hb = 0;
-      prevhb = 0;
+      prevc = 0;
 #pragma unroll
       for (int b = 0; b < PL; ++b) cnt[b] = 0;
       synbits = ring_syn[e * G + q];
       if constexpr (MODE == MODE_MAIN) {
         shot = (long long)(uint32_t)ring_meta[e * META + 0] | ((long long)ring_meta[e * META + 1] << 32);
       } else {
+        tbits = ring_tb[e * G + q];
         shot = ring_meta[e * META + 0];
         rec = ring_meta[e * META + 2];
         trial = ring_meta[e * META + 3];
         main_iters = ring_meta[e * META + 4];
-        tbits = 0;
-        for (int j = 0; j < a.k; ++j) {
-          const int v = ring_tv[e * KMAX + j];
-          if (v >= 0 && (v & (G - 1)) == q) tbits |= 1u << (v >> LG);
-        }
-      }
-    }
-    // residual of a taken slot starts at its syndrome: set my bits
-    const uint32_t mybit = 1u << (lane & 31);
-#pragma unroll
-    for (int k = 0; k < IC; ++k) {
-      uint32_t* w = &resid[k * 2 + (lane >> 5)];
-      if (take) {
-        if ((synbits >> k) & 1u) atomicOr(w, mybit);
-        else atomicAnd(w, ~mybit);
       }
     }
     // messages of taken slots: v2c = L (c2v = 0 before the first iteration)
@@ -344,36 +360,15 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
     while (tb) {
       const int ld = __ffsll((long long)tb) - 1;
       tb &= tb - 1ull;
-      const int sd = ld >> LG;
-      const uint32_t sofs = (uint32_t)sizeof(Real) * (uint32_t)(sd * MS);
+      const int sbase = (ld >> LG) * MS + lane;
 #pragma unroll
-      for (int r = 0; r < NRESET; ++r)
-        if (rst_off[r] != 0xffffffffu)
-          *reinterpret_cast<Real*>(smem + rst_off[r] + sofs) = rst_val[r];
-    }
-    if constexpr (MODE != MODE_MAIN) {
-      __syncthreads();
-      // s' = s + t H^T: toggle the checks of every bit in t
-      if (take) {
-        for (int j = q; j < a.k; j += G) {
-          const int v = ring_tv[e * KMAX + j];
-          if (v >= 0) {
+      for (int j = 0; j < W; ++j)
 #pragma unroll
-            for (int i = 0; i < DV; ++i) {
-              const int c = chk[v * DV + i];
-              const int ol = (d << LG) | (c & (G - 1));
-              atomicXor(&resid[(c >> LG) * 2 + (ol >> 5)], 1u << (ol & 31));
-            }
+        for (int h = 0; h < MSB; ++h)
+          if (64 * h + lane < MS) {
+            if constexpr (UL) msg[j * CI + sbase + 64 * h] = Lu;
+            else msg[j * CI + sbase + 64 * h] = rst_val[j][h];
           }
-        }
-      }
-      __syncthreads();
-      if (take) {
-        uint32_t s2 = 0;
-#pragma unroll
-        for (int k = 0; k < IC; ++k) s2 |= ((resid[k * 2 + (lane >> 5)] >> (lane & 31)) & 1u) << k;
-        synbits = s2;
-      }
     }
   };
 
@@ -392,36 +387,43 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
     if (!any_active && exhausted && pend_n == 0 && tail == head) break;
 
     // ---- check phase: c2v from v2c, Eq. (c2v) ----
-    Real alpha;
-    if (a.alpha > 0.0) alpha = R::from_double(a.alpha);
-    else alpha = R::from_double(1.0 - ldexp(1.0, -(iter + 1)));
+    Real alpha = alpha_fixed;
+    if (adaptive) alpha = R::adaptive_alpha(iter + 1);
+    {
+      // loads of item k+1 are issued before the stores of item k
+      Real x[2][W];
 #pragma unroll
-    for (int k = 0; k < IC; ++k) {
-      Real x[W];
+      for (int j = 0; j < W; ++j) x[0][j] = msg[j * CI + cbase];
 #pragma unroll
-      for (int j = 0; j < W; ++j) x[j] = msg[j * CI + cbase + G * k];
-      Real m1 = R::minr(R::absr(x[0]), R::absr(x[1]));
-      Real m2 = R::maxr(R::absr(x[0]), R::absr(x[1]));
-      uint32_t P = R::sw(x[0]) ^ R::sw(x[1]);
+      for (int k = 0; k < IC; ++k) {
+        Real (&xc)[W] = x[k & 1];
+        if (k + 1 < IC) {
 #pragma unroll
-      for (int j = 2; j < W; ++j) {
-        m2 = R::med3(m1, m2, R::absr(x[j]));
-        m1 = R::minr(m1, R::absr(x[j]));
-        P ^= R::sw(x[j]);
-      }
-      P ^= synbits << (31 - k);                         // (-1)^{s_c}
-      Real s1 = R::flip(alpha * m1, P), s2 = R::flip(alpha * m2, P);
-      R::opaque(s1);
-      R::opaque(s2);
+          for (int j = 0; j < W; ++j) x[(k + 1) & 1][j] = msg[j * CI + cbase + G * (k + 1)];
+        }
+        Real m1 = R::minr(R::absr(xc[0]), R::absr(xc[1]));
+        Real m2 = R::maxr(R::absr(xc[0]), R::absr(xc[1]));
+        uint32_t P = R::sw(xc[0]) ^ R::sw(xc[1]);
 #pragma unroll
-      for (int j = 0; j < W; ++j) {
-        // the minimum over the other edges: min2 on the edge holding min1
-        const Real o = R::flip(R::absr(x[j]) == m1 ? s2 : s1, R::sw(x[j]));
-        msg[j * CI + cbase + G * k] = o;
-        if constexpr (TRACE) {
-          const int c = q + G * k;
-          if (d == 0 && active && c < M)
-            reinterpret_cast<Real*>(a.trace_c2v)[(long long)iter * M * W + c * W + j] = o;
+        for (int j = 2; j < W; ++j) {
+          m2 = R::med3(m1, m2, R::absr(xc[j]));
+          m1 = R::minr(m1, R::absr(xc[j]));
+          P ^= R::sw(xc[j]);
+        }
+        P ^= synbits << (31 - k);                         // (-1)^{s_c}
+        Real s1 = R::flip(alpha * m1, P), s2 = R::flip(alpha * m2, P);
+        R::opaque(s1);
+        R::opaque(s2);
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+          // the minimum over the other edges: min2 on the edge holding min1
+          const Real o = R::flip(R::absr(xc[j]) == m1 ? s2 : s1, R::sw(xc[j]));
+          msg[j * CI + cbase + G * k] = o;
+          if constexpr (TRACE) {
+            const int c = q + G * k;
+            if (d == 0 && active && c < M)
+              reinterpret_cast<Real*>(a.trace_c2v)[(long long)iter * M * W + c * W + j] = o;
+          }
         }
       }
     }
@@ -430,35 +432,41 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
 
     // ---- bit phase: marginal, hard decision, next v2c ----
     uint32_t nhb = 0;
+    {
+      // every gather is issued before the first store of this phase
+      Real cv[IV][DV];
 #pragma unroll
-    for (int k = 0; k < IV; ++k) {
-      Real c[DV];
+      for (int k = 0; k < IV; ++k)
 #pragma unroll
-      for (int j = 0; j < DV; ++j) c[j] = *reinterpret_cast<const Real*>(smem + off[k][j]);
-      // prefix sums in ascending check order starting from the channel LLR
-      Real pre[DV + 1];
-      pre[0] = Lv[k];
+        for (int j = 0; j < DV; ++j) cv[k][j] = *reinterpret_cast<const Real*>(smem + off[k][j]);
 #pragma unroll
-      for (int j = 0; j < DV; ++j) pre[j + 1] = pre[j] + c[j];
-      const Real lout = pre[DV];
+      for (int k = IV - 1; k >= 0; --k) {
+        // prefix sums in ascending check order starting from the channel LLR
+        Real pre[DV + 1];
+        pre[0] = Lv[UL ? 0 : k];
 #pragma unroll
-      for (int j = 0; j < DV; ++j) {
-        Real acc = pre[j];
+        for (int j = 0; j < DV; ++j) pre[j + 1] = pre[j] + cv[k][j];
+        const Real lout = pre[DV];
 #pragma unroll
-        for (int i = j + 1; i < DV; ++i) acc = acc + c[i];
-        *reinterpret_cast<Real*>(smem + off[k][j]) = acc;   // v2c for the next iteration
-      }
-      nhb |= (lout > (Real)0 ? 0u : 1u) << k;
-      if constexpr (TRACE) {
-        const int v = q + G * k;
-        if (d == 0 && active && v < N) reinterpret_cast<Real*>(a.trace_lout)[(long long)iter * N + v] = lout;
+        for (int j = 0; j < DV; ++j) {
+          Real acc = pre[j];
+#pragma unroll
+          for (int i = j + 1; i < DV; ++i) acc = acc + cv[k][i];
+          *reinterpret_cast<Real*>(smem + off[k][j]) = acc;   // v2c for the next iteration
+        }
+        // shift the hard decision of item k in (items run from IV-1 down to 0)
+        nhb = __builtin_amdgcn_alignbit(nhb, R::nonpos_msb(lout), 31);
+        if constexpr (TRACE) {
+          const int v = q + G * k;
+          if (d == 0 && active && v < N) reinterpret_cast<Real*>(a.trace_lout)[(long long)iter * N + v] = lout;
+        }
       }
     }
-    hb = nhb & vmask;
-    const uint32_t flips = active ? (hb ^ prevhb) : 0u;
-    prevhb = hb;
+    if (active) hb = nhb & vmask;       // an idle slot keeps its bits, so u stays H e
     if constexpr (MODE == MODE_MAIN) {
-      uint32_t carry = flips;
+      const uint32_t fc = hb ^ prevc;
+      prevc = hb;
+      uint32_t carry = fc;
 #pragma unroll
       for (int b = 0; b < PL; ++b) {
         const uint32_t t = cnt[b] & carry;
@@ -466,9 +474,10 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
         carry = t;
       }
     }
-    // residual toggles for bits whose hard decision changed
+    // u follows the hard decisions: toggle the checks of every bit that changed
     {
-      uint32_t f = flips;
+      uint32_t f = hb ^ prevt;
+      prevt = hb;
       while (f) {
         const int k = __builtin_ctz(f);
         f &= f - 1u;
@@ -477,16 +486,16 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
         for (int i = 0; i < DV; ++i) {
           const int c = chk[v * DV + i];
           const int ol = (d << LG) | (c & (G - 1));
-          atomicXor(&resid[(c >> LG) * 2 + (ol >> 5)], 1u << (ol & 31));
+          atomicXor(&uw[(c >> LG) * 2 + (ol >> 5)], 1u << (ol & 31));
         }
       }
     }
     __syncthreads();
 
-    // ---- syndrome test of every slot ----
+    // ---- syndrome test of every slot: u == s on all its checks ----
     uint32_t un = 0;
 #pragma unroll
-    for (int k = 0; k < IC; ++k) un |= resid[k * 2 + (lane >> 5)] >> (lane & 31);
+    for (int k = 0; k < IC; ++k) un |= (uw[k * 2 + (lane >> 5)] >> (lane & 31)) ^ (synbits >> k);
     un &= 1u;
     const unsigned long long ub = __ballot(un != 0u);
     const unsigned long long gm = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
@@ -524,7 +533,7 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
           int f = 0;
           if (need && q == 0) f = (int)atomicAdd(&a.counters[CNT_FAILED], 1ull);
           f = __shfl(f, d * G);
-          int32_t* r = a.records + (long long)f * a.rec_stride;
+          int32_t* r = a.records + (long long)f * rstride;
           if (need) {
             if (q == 0) {
               r[REC_SHOT] = (int32_t)shot;
@@ -532,19 +541,27 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
               r[REC_MAIN_CONV] = conv ? 1 : 0;
               a.keys[f] = KEY_NONE;
             }
-            r[REC_HDR + KMAX + q] = (int32_t)synbits;
+            r[REC_HDR + q] = (int32_t)synbits;
           }
+          // top(flip_count, |Phi|), one bit per round
           for (int j = 0; j < a.k; ++j) {
             uint32_t best = 0;
 #pragma unroll
             for (int k = 0; k < IV; ++k) best = key[k] > best ? key[k] : best;
+            best = group_reduce<G>(best, OpMax());
+            const int v = best ? 0xffff - (int)(best & 0xffffu) : 0;   // best > 0 while k <= N
+            // my share of column v: my checks among its DV checks, and v itself
+            uint32_t tw = 0;
 #pragma unroll
-            for (int o = G / 2; o >= 1; o >>= 1) {
-              const uint32_t other = (uint32_t)__shfl_xor((int)best, o);
-              best = other > best ? other : best;
+            for (int i = 0; i < DV; ++i) {
+              const int c = chk[v * DV + i];
+              if ((c & (G - 1)) == q) tw ^= 1u << (c >> LG);
             }
-            const int v = 0xffff - (int)(best & 0xffffu);
-            if (need && q == (j & (G - 1))) r[REC_HDR + j] = v;
+            if ((v & (G - 1)) == q) tw |= (uint32_t)((v >> LG) + 1) << 16;
+            if (need) {
+              r[REC_HDR + G + j * G + q] = (int32_t)tw;
+              if (q == 0) r[REC_HDR + G + a.k * G + j] = v;
+            }
             if ((v & (G - 1)) == q) {
 #pragma unroll
               for (int k = 0; k < IV; ++k)
@@ -554,9 +571,7 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
         }
       } else if constexpr (MODE == MODE_CAND) {
         // weight of the undone correction e = e' + t over the slot
-        int w = __popc((hb ^ tbits) & vmask);
-#pragma unroll
-        for (int o = G / 2; o >= 1; o >>= 1) w += __shfl_xor(w, o);
+        const uint32_t w = group_reduce<G>((uint32_t)__popc((hb ^ tbits) & vmask), OpAdd());
         if (fin && q == 0) {
           st_iters += (unsigned long long)iter;
           if (conv) {
@@ -605,48 +620,55 @@ __global__ void bpsf_reset_counters(unsigned long long* c)
 
 // ------------------------------------------------------------ dispatch --
 
-template <typename Real, int D, int IC, int IV, int W, int DV>
+template <typename Real, int D, int IC, int IV, int W, int DV, bool UL>
 static int launch_tile(int mode, bool trace, const Args& a, int grid, void* stream)
 {
   using T = TileShape<D, IC, IV, W, DV>;
-  const LdsLayout lay = lds_layout(sizeof(Real), W, a.CI, T::RW, a.N, DV, T::RING, T::META, T::KMAX, T::G);
+  const LdsLayout lay = lds_layout(sizeof(Real), W, T::CI, T::RW, a.N, DV, T::RING, T::META, T::KMAX, T::G);
   const size_t sh = lay.total;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (mode == MODE_MAIN && trace)
-    hipLaunchKernelGGL((bpsf_kernel<Real, D, IC, IV, W, DV, MODE_MAIN, true>), dim3(grid), dim3(64), sh, st, a);
+    hipLaunchKernelGGL((bpsf_kernel<Real, D, IC, IV, W, DV, UL, MODE_MAIN, true>), dim3(grid), dim3(64), sh, st, a);
   else if (mode == MODE_MAIN)
-    hipLaunchKernelGGL((bpsf_kernel<Real, D, IC, IV, W, DV, MODE_MAIN, false>), dim3(grid), dim3(64), sh, st, a);
+    hipLaunchKernelGGL((bpsf_kernel<Real, D, IC, IV, W, DV, UL, MODE_MAIN, false>), dim3(grid), dim3(64), sh, st, a);
   else if (mode == MODE_CAND)
-    hipLaunchKernelGGL((bpsf_kernel<Real, D, IC, IV, W, DV, MODE_CAND, false>), dim3(grid), dim3(64), sh, st, a);
+    hipLaunchKernelGGL((bpsf_kernel<Real, D, IC, IV, W, DV, UL, MODE_CAND, false>), dim3(grid), dim3(64), sh, st, a);
   else
-    hipLaunchKernelGGL((bpsf_kernel<Real, D, IC, IV, W, DV, MODE_EMIT, false>), dim3(grid), dim3(64), sh, st, a);
+    hipLaunchKernelGGL((bpsf_kernel<Real, D, IC, IV, W, DV, UL, MODE_EMIT, false>), dim3(grid), dim3(64), sh, st, a);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <typename Real, int D, int IC, int IV, int W, int DV>
+template <typename Real, int D, int IC, int IV, int W, int DV, bool UL>
 static int occupancy_tile(int mode, const Args& a, int* blocks_per_cu)
 {
   using T = TileShape<D, IC, IV, W, DV>;
-  const LdsLayout lay = lds_layout(sizeof(Real), W, a.CI, T::RW, a.N, DV, T::RING, T::META, T::KMAX, T::G);
+  const LdsLayout lay = lds_layout(sizeof(Real), W, T::CI, T::RW, a.N, DV, T::RING, T::META, T::KMAX, T::G);
   hipError_t e;
   if (mode == MODE_MAIN)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, bpsf_kernel<Real, D, IC, IV, W, DV, MODE_MAIN, false>, 64, lay.total);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, bpsf_kernel<Real, D, IC, IV, W, DV, UL, MODE_MAIN, false>, 64, lay.total);
   else if (mode == MODE_CAND)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, bpsf_kernel<Real, D, IC, IV, W, DV, MODE_CAND, false>, 64, lay.total);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, bpsf_kernel<Real, D, IC, IV, W, DV, UL, MODE_CAND, false>, 64, lay.total);
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, bpsf_kernel<Real, D, IC, IV, W, DV, MODE_EMIT, false>, 64, lay.total);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, bpsf_kernel<Real, D, IC, IV, W, DV, UL, MODE_EMIT, false>, 64, lay.total);
   return e == hipSuccess ? 0 : -1;
 }
 
-#define BPSF_TILE_CASE(D_, IC_, IV_, W_, DV_)                                                   \
-  if (t.D == D_ && t.IC == IC_ && t.IV == IV_ && t.W == W_ && t.DV == DV_) {                    \
-    if (fp64) return what == 0 ? launch_tile<double, D_, IC_, IV_, W_, DV_>(mode, trace, a, grid, st) \
-                               : occupancy_tile<double, D_, IC_, IV_, W_, DV_>(mode, a, out);   \
-    return what == 0 ? launch_tile<float, D_, IC_, IV_, W_, DV_>(mode, trace, a, grid, st)     \
-                     : occupancy_tile<float, D_, IC_, IV_, W_, DV_>(mode, a, out);             \
+template <typename Real, int D, int IC, int IV, int W, int DV>
+static int tile_call(int what, bool ul, int mode, bool trace, const Args& a, int grid, void* st, int* out)
+{
+  if (ul) return what == 0 ? launch_tile<Real, D, IC, IV, W, DV, true>(mode, trace, a, grid, st)
+                            : occupancy_tile<Real, D, IC, IV, W, DV, true>(mode, a, out);
+  return what == 0 ? launch_tile<Real, D, IC, IV, W, DV, false>(mode, trace, a, grid, st)
+                   : occupancy_tile<Real, D, IC, IV, W, DV, false>(mode, a, out);
+}
+
+#define BPSF_TILE_CASE(D_, IC_, IV_, W_, DV_)                                                          \
+  if (t.D == D_ && t.IC == IC_ && t.IV == IV_ && t.W == W_ && t.DV == DV_) {                           \
+    return fp64 ? tile_call<double, D_, IC_, IV_, W_, DV_>(what, ul, mode, trace, a, grid, st, out)    \
+                : tile_call<float, D_, IC_, IV_, W_, DV_>(what, ul, mode, trace, a, grid, st, out);    \
   }
 
-int tile_dispatch(int what, const TileDesc& t, bool fp64, int mode, bool trace, const Args& a, int grid,
+int tile_dispatch(int what, const TileDesc& t, bool fp64, bool ul, int mode, bool trace, const Args& a, int grid,
                   void* st, int* out)
 {
   BPSF_TILE_LIST(BPSF_TILE_CASE)

@@ -6,6 +6,16 @@
 
 namespace bpsf {
 
+// Slot stride: at least G*IC entries and congruent to G modulo 32, so the 32
+// lanes of each half-wave hit 32 distinct banks in the check phase.
+constexpr int slot_stride_c(int G, int IC)
+{
+  int ms = G * IC;
+  const int want = G % 32;
+  while (ms % 32 != want) ++ms;
+  return ms;
+}
+
 // D: decodes (slots) per wave; IC / IV: check / bit items per lane;
 // W: ELL row width; DV: column weight.
 template <int D_, int IC_, int IV_, int W_, int DV_>
@@ -19,6 +29,9 @@ struct TileShape {
   static constexpr int KMAX = 16;                   // largest |Phi|
   static constexpr int KG = (KMAX + G - 1) / G;     // Phi entries per lane
   static constexpr int RW = IC * 2;                 // residual words (64 bits per check item)
+  static constexpr int MS = slot_stride_c(G, IC);   // message entries per slot and edge position
+  static constexpr int CI = D * MS;                 // entries per edge position
+  static constexpr int MSB = (MS + 63) / 64;        // 64-lane blocks covering one slot's stride
   static_assert(D * G == 64, "D must divide 64");
   static_assert(IC <= 32 && IV <= 32, "items per lane must fit a 32-bit mask");
   static_assert(W >= 2 && DV >= 1, "row weight >= 2");
@@ -59,31 +72,17 @@ __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int W, int CI, i
   o = lds_align16(o);
   L.ring_meta = o;
   o += 4u * (uint32_t)(RING * META);
-  L.ring_tv = o;
-  o += 4u * (uint32_t)(RING * KMAX);
+  L.ring_tv = o;                                       // trial bits per lane of every entry
+  o += 4u * (uint32_t)(RING * (KMAX > G ? KMAX : G));
   L.ring_syn = o;
   o += 4u * (uint32_t)(RING * G);
   L.total = lds_align16(o);
   return L;
 }
 
-// Slot stride: at least G*IC entries and congruent to G modulo 32, so the 32
-// lanes of each half-wave hit 32 distinct banks in the check phase.
-inline int slot_stride(int G, int IC)
-{
-  int ms = G * IC;
-  const int want = G % 32;
-  while (ms % 32 != want) ++ms;
-  return ms;
-}
-
-// Reset entries per lane the kernel reserves registers for.
-template <class T>
-constexpr int reset_slots() { return (T::W * (T::G * T::IC + 31) + 63) / 64; }
-
 struct Args;
-int tile_dispatch(int what, const TileDesc& t, bool fp64, int mode, bool trace, const Args& a, int grid,
-                  void* stream, int* out);
+int tile_dispatch(int what, const TileDesc& t, bool fp64, bool uniform_llr, int mode, bool trace,
+                  const Args& a, int grid, void* stream, int* out);
 int reset_counters(unsigned long long* c, void* stream);
 
 }  // namespace bpsf
