@@ -51,6 +51,63 @@ def traffic_from_profile(phase: str, launches_bytes_key: str = "hbm_bytes_per_di
     return rec.get("phases", {}).get(phase, {}).get(launches_bytes_key)
 
 
+COPY_BYTES = 1 << 30
+
+
+def copy_calibration(reps: int = 3):
+    """A plain device copy of known size, profiled beside the decoder to scale
+    FETCH_SIZE / WRITE_SIZE into bytes."""
+    import torch
+    src = torch.ones(COPY_BYTES, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "reps": reps}), flush=True)
+
+
+def _pmc_per_dispatch(csv_path: str, counter: str):
+    """Mean counter value per dispatch, by decode phase (and for the copy kernel)."""
+    import csv
+    acc, seen = {}, {}
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            kn = r["Kernel_Name"]
+            if "bpsf_kernel" in kn:
+                ph = "main" if ", 0, false>" in kn else ("trials" if ", 1, false>" in kn else "rerun")
+            elif "copy" in kn.lower():
+                ph = "copy"
+            else:
+                continue
+            acc[ph] = acc.get(ph, 0.0) + float(r["Counter_Value"])
+            seen.setdefault(ph, set()).add(r["Dispatch_Id"])
+    return {ph: acc[ph] / len(seen[ph]) for ph in acc}
+
+
+def traffic_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, out_path):
+    """Per-dispatch HBM bytes of every phase from two counter runs, scaled by
+    what the same counters read for a plain copy of COPY_BYTES."""
+    fe = _pmc_per_dispatch(fetch_csv, "FETCH_SIZE")
+    wr = _pmc_per_dispatch(write_csv, "WRITE_SIZE")
+    cf = _pmc_per_dispatch(copy_fetch_csv, "FETCH_SIZE")["copy"]
+    cw = _pmc_per_dispatch(copy_write_csv, "WRITE_SIZE")["copy"]
+    kib = COPY_BYTES / 1024.0
+    f_scale, w_scale = kib / cf, kib / cw
+    rec = {"kernel_src_sha": kernel_hash(), "copy_fetch_kib": cf, "copy_write_kib": cw,
+           "fetch_scale": f_scale, "write_scale": w_scale, "phases": {}}
+    for ph in fe:
+        if ph == "copy":
+            continue
+        b = (fe[ph] * f_scale + wr.get(ph, 0.0) * w_scale) * 1024.0
+        rec["phases"][ph] = {"fetch_kib_per_dispatch": fe[ph], "write_kib_per_dispatch": wr.get(ph, 0.0),
+                             "hbm_bytes_per_dispatch": b}
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec), flush=True)
+
+
 def cpu_baseline(h, syn, p, prm, seconds: float):
     from oracle.oracle import OracleLib
     threads = min(os.cpu_count() or 1, 16)
@@ -76,7 +133,17 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-calls", type=int, default=200)
+    ap.add_argument("--copy-calibration", action="store_true", help="run only the plain copy used to scale counters")
+    ap.add_argument("--traffic-summary", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
+                                                           "COPY_WRITE_CSV", "OUT_JSON"),
+                    help="write the per-phase HBM traffic summary from rocprofv3 counter CSVs")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary)
+        return
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(shots shard independently across GPUs; see the design notes)", file=sys.stderr)
