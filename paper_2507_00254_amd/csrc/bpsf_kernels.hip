@@ -17,8 +17,8 @@
 //     stride MS per slot and CI = D*MS per position, so check-phase accesses
 //     are consecutive words and bit-phase gathers are mostly consecutive on
 //     quasi-cyclic codes;
-//   * the syndrome test is incremental: an LDS bitmap u = H e (one bit per
-//     check, laid out like the check items) is toggled only when a hard
+//   * the syndrome test is incremental: u = H e (one LDS word per check, laid
+//     out like the check items, bit 0 used) is toggled only when a hard
 //     decision flips, and a slot has converged when u equals its syndrome; a
 //     refilled slot keeps its previous hard decisions as the toggle baseline,
 //     so u never needs re-initializing;
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
   static_assert(IC <= 16, "check items are packed into 16-bit column masks");
 
   extern __shared__ __align__(16) unsigned char smem[];
-  const LdsLayout lay = lds_layout(sizeof(Real), W, CI, T::RW, a.N, DV, RING, META, KMAX, G);
+  const LdsLayout lay = lds_layout(sizeof(Real), W, CI, CI, a.N, DV, RING, META, KMAX, G);
   Real* msg = reinterpret_cast<Real*>(smem + lay.msg);
   uint32_t* uw = reinterpret_cast<uint32_t*>(smem + lay.resid);
   uint16_t* chk = reinterpret_cast<uint16_t*>(smem + lay.chk);
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
 
   // ---- per-code tables into LDS ------------------------------------------
   for (int i = lane; i < N * DV; i += 64) chk[i] = a.var_chk[i];
-  for (int i = lane; i < T::RW; i += 64) uw[i] = 0u;
+  for (int i = lane; i < CI; i += 64) uw[i] = 0u;
 
   // ---- per-lane constants -------------------------------------------------
   // bit items: channel LLR and the byte offsets of their DV edges
@@ -483,11 +483,7 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
         f &= f - 1u;
         const int v = q + (k << LG);
 #pragma unroll
-        for (int i = 0; i < DV; ++i) {
-          const int c = chk[v * DV + i];
-          const int ol = (d << LG) | (c & (G - 1));
-          atomicXor(&uw[(c >> LG) * 2 + (ol >> 5)], 1u << (ol & 31));
-        }
+        for (int i = 0; i < DV; ++i) atomicXor(&uw[d * MS + chk[v * DV + i]], 1u);
       }
     }
     __syncthreads();
@@ -495,7 +491,7 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
     // ---- syndrome test of every slot: u == s on all its checks ----
     uint32_t un = 0;
 #pragma unroll
-    for (int k = 0; k < IC; ++k) un |= (uw[k * 2 + (lane >> 5)] >> (lane & 31)) ^ (synbits >> k);
+    for (int k = 0; k < IC; ++k) un |= uw[cbase + G * k] ^ (synbits >> k);
     un &= 1u;
     const unsigned long long ub = __ballot(un != 0u);
     const unsigned long long gm = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
@@ -624,7 +620,7 @@ template <typename Real, int D, int IC, int IV, int W, int DV, bool UL>
 static int launch_tile(int mode, bool trace, const Args& a, int grid, void* stream)
 {
   using T = TileShape<D, IC, IV, W, DV>;
-  const LdsLayout lay = lds_layout(sizeof(Real), W, T::CI, T::RW, a.N, DV, T::RING, T::META, T::KMAX, T::G);
+  const LdsLayout lay = lds_layout(sizeof(Real), W, T::CI, T::CI, a.N, DV, T::RING, T::META, T::KMAX, T::G);
   const size_t sh = lay.total;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (mode == MODE_MAIN && trace)
@@ -642,7 +638,7 @@ template <typename Real, int D, int IC, int IV, int W, int DV, bool UL>
 static int occupancy_tile(int mode, const Args& a, int* blocks_per_cu)
 {
   using T = TileShape<D, IC, IV, W, DV>;
-  const LdsLayout lay = lds_layout(sizeof(Real), W, T::CI, T::RW, a.N, DV, T::RING, T::META, T::KMAX, T::G);
+  const LdsLayout lay = lds_layout(sizeof(Real), W, T::CI, T::CI, a.N, DV, T::RING, T::META, T::KMAX, T::G);
   hipError_t e;
   if (mode == MODE_MAIN)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, bpsf_kernel<Real, D, IC, IV, W, DV, UL, MODE_MAIN, false>, 64, lay.total);

@@ -28,7 +28,6 @@ struct TileShape {
   static constexpr int META = 8;                    // ints per ring entry header
   static constexpr int KMAX = 16;                   // largest |Phi|
   static constexpr int KG = (KMAX + G - 1) / G;     // Phi entries per lane
-  static constexpr int RW = IC * 2;                 // residual words (64 bits per check item)
   static constexpr int MS = slot_stride_c(G, IC);   // message entries per slot and edge position
   static constexpr int CI = D * MS;                 // entries per edge position
   static constexpr int MSB = (MS + 63) / 64;        // 64-lane blocks covering one slot's stride
@@ -64,7 +63,7 @@ __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int W, int CI, i
   L.msg = o;                                           // W x CI messages + 64-entry sink
   o += (uint32_t)real_bytes * (uint32_t)(W * CI + 64);
   o = lds_align16(o);
-  L.resid = o;                                         // residual bitmap
+  L.resid = o;                                         // u = H e, one word per check of every slot
   o += 4u * (uint32_t)RW;
   o = lds_align16(o);
   L.chk = o;                                           // checks of every bit (u16)
