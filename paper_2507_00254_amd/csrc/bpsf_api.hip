@@ -41,11 +41,6 @@ int fail(int code, const char* fmt, ...)
     if (e_ != hipSuccess) return fail(BPSF_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-const TileDesc kTiles[] = {
-#define BPSF_TILE_DESC(D_, IC_, IV_, W_, DV_) {D_, IC_, IV_, W_, DV_},
-    BPSF_TILE_LIST(BPSF_TILE_DESC)
-#undef BPSF_TILE_DESC
-};
 
 struct DevBuf {
   void* p = nullptr;
@@ -79,6 +74,7 @@ struct bpsf_code_s {
   DevBuf masks;
   // scratch
   DevBuf records, keys, counters;
+  int tuned_D = 0;            // decodes per wave chosen by bpsf_autotune (0: default)
   // optional per-phase timing: events[i] marks the boundary before phase i
   bool timing = false;
   bool timed_last = false;
@@ -94,23 +90,38 @@ struct bpsf_code_s {
 
 namespace {
 
+// Does the code fit family `fam` at D decodes per wave?
+bool tile_fits(const bpsf_code_s* c, int fam, int D)
+{
+  const FamilyDesc f = family_desc(fam);
+  if (f.W != c->W || f.DV != c->DV) return false;
+  if (D < 1 || D > MAX_D || (D & (D - 1))) return false;
+  const int G = 64 / D;
+  return c->M <= G * f.IC && c->N <= G * f.IV && c->N * f.DV <= 65535;
+}
+
+// Default tile: a family the code fits, at the most decodes per wave (the
+// handle's tuned or forced D when set).
 int pick_tile(const bpsf_code_s* c, TileDesc* out)
 {
-  int best = -1;
-  for (int i = 0; i < (int)(sizeof kTiles / sizeof kTiles[0]); ++i) {
-    const TileDesc& t = kTiles[i];
-    if (t.W != c->W || t.DV != c->DV) continue;
-    const int G = 64 / t.D;
-    if ((c->M + G - 1) / G > t.IC || (c->N + G - 1) / G > t.IV) continue;
-    if (c->N * t.DV > 65535) continue;
-    if (best < 0) { best = i; continue; }
-    const TileDesc& b = kTiles[best];
-    // more slots first, then fewer padded items
-    if (t.D > b.D || (t.D == b.D && t.IC * t.IV < b.IC * b.IV)) best = i;
+  for (int fam = 0; fam < family_count(); ++fam) {
+    if (c->tuned_D > 0 && tile_fits(c, fam, c->tuned_D)) {
+      *out = TileDesc{fam, c->tuned_D};
+      return 0;
+    }
+    for (int D = MAX_D; D >= 1; D >>= 1)
+      if (tile_fits(c, fam, D)) {
+        *out = TileDesc{fam, D};
+        return 0;
+      }
   }
-  if (best < 0) return -1;
-  *out = kTiles[best];
-  return 0;
+  return -1;
+}
+
+size_t tile_lds(const bpsf_code_s* c, const TileDesc& t, bool fp64)
+{
+  const FamilyDesc f = family_desc(t.fam);
+  return lds_layout(fp64 ? 8 : 4, f.W, 64 * f.IC, c->M, c->N, f.DV, t.D, c->uniform, 8).total;
 }
 
 // Trial vectors of Algorithm 1 as k-bit masks over Phi, in trial order.
@@ -204,6 +215,7 @@ int update_masks(bpsf_code_s* c, const bpsf_params* p)
 struct Plan {
   TileDesc tile;
   Args args;
+  size_t lds;
   int grid[3];
 };
 
@@ -217,12 +229,15 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
   memset(&a, 0, sizeof a);
   a.M = c->M;
   a.N = c->N;
+  a.D = t.D;
   a.var_chk = static_cast<const uint16_t*>(c->var_chk.p);
   a.var_pos = static_cast<const uint8_t*>(c->var_pos.p);
   a.ell_col = static_cast<const int32_t*>(c->ell_col.p);
   a.llr = p->precision == BPSF_PREC_FP64 ? c->llr64.p : c->llr32.p;
   a.llr_uniform = c->llr_uniform;
   a.shots = shots;
+  a.syn_stride = c->M;
+  a.corr_stride = c->N;
   a.max_iter = p->max_iter;
   a.cand_max_iter = p->k > 0 ? p->cand_max_iter : 1;
   a.k = p->k;
@@ -239,16 +254,17 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
   const int64_t cap = shots > 0 ? shots : 1;
   if (c->records.ensure(sizeof(int32_t) * (size_t)a.rec_stride * (size_t)cap) ||
       c->keys.ensure(sizeof(unsigned long long) * (size_t)cap) ||
-      c->counters.ensure(sizeof(unsigned long long) * CNT_WORDS))
+      c->counters.ensure(sizeof(unsigned long long) * CNT_WORDS * MIX_MAX_CODES))
     return fail(BPSF_ENOMEM, "scratch for %lld shots", (long long)shots);
   a.records = static_cast<int32_t*>(c->records.p);
   a.rec_cap = cap;
   a.keys = static_cast<unsigned long long*>(c->keys.p);
   a.counters = static_cast<unsigned long long*>(c->counters.p);
   const bool fp64 = p->precision == BPSF_PREC_FP64;
+  pl->lds = tile_lds(c, t, fp64);
   for (int mode = 0; mode < 3; ++mode) {
     int per_cu = 0;
-    if (tile_dispatch(1, t, fp64, c->uniform, mode, false, a, 0, nullptr, &per_cu) || per_cu < 1)
+    if (tile_dispatch(1, t, fp64, c->uniform, mode, false, a, pl->lds, 0, nullptr, &per_cu) || per_cu < 1)
       return fail(BPSF_EDEVICE, "occupancy query failed for mode %d", mode);
     pl->grid[mode] = per_cu * c->cus;
   }
@@ -373,16 +389,16 @@ int bpsf_decode(bpsf_code c, const uint8_t* syndromes, const double* priors, int
   a.iterations = iterations;
   const bool fp64 = p->precision == BPSF_PREC_FP64;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (reset_counters(a.counters, stream)) return fail(BPSF_EDEVICE, "counter reset launch");
+  if (reset_counters(a.counters, CNT_WORDS, stream)) return fail(BPSF_EDEVICE, "counter reset launch");
   if (c->timing) HIP_OK(hipEventRecord(c->ev[0], st));
-  if (tile_dispatch(0, pl.tile, fp64, c->uniform, MODE_MAIN, false, a, pl.grid[MODE_MAIN], stream, nullptr))
+  if (tile_dispatch(0, pl.tile, fp64, c->uniform, MODE_MAIN, false, a, pl.lds, pl.grid[MODE_MAIN], stream, nullptr))
     return fail(BPSF_EDEVICE, "first-BP launch failed");
   if (c->timing) HIP_OK(hipEventRecord(c->ev[1], st));
   if (p->k > 0) {
-    if (tile_dispatch(0, pl.tile, fp64, c->uniform, MODE_CAND, false, a, pl.grid[MODE_CAND], stream, nullptr))
+    if (tile_dispatch(0, pl.tile, fp64, c->uniform, MODE_CAND, false, a, pl.lds, pl.grid[MODE_CAND], stream, nullptr))
       return fail(BPSF_EDEVICE, "trial launch failed");
     if (c->timing) HIP_OK(hipEventRecord(c->ev[2], st));
-    if (tile_dispatch(0, pl.tile, fp64, c->uniform, MODE_EMIT, false, a, pl.grid[MODE_EMIT], stream, nullptr))
+    if (tile_dispatch(0, pl.tile, fp64, c->uniform, MODE_EMIT, false, a, pl.lds, pl.grid[MODE_EMIT], stream, nullptr))
       return fail(BPSF_EDEVICE, "re-run launch failed");
     if (c->timing) HIP_OK(hipEventRecord(c->ev[3], st));
   }
@@ -469,8 +485,8 @@ int bpsf_bp_trace(bpsf_code c, const uint8_t* syndrome, const double* priors, co
   a.iterations = static_cast<int32_t*>(dit.p);
   a.trace_lout = dl.p;
   a.trace_c2v = dc.p;
-  if (reset_counters(a.counters, nullptr)) return fail(BPSF_EDEVICE, "counter reset launch");
-  if (tile_dispatch(0, pl.tile, q.precision == BPSF_PREC_FP64, c->uniform, MODE_MAIN, true, a, 1, nullptr, nullptr))
+  if (reset_counters(a.counters, CNT_WORDS, nullptr)) return fail(BPSF_EDEVICE, "counter reset launch");
+  if (tile_dispatch(0, pl.tile, q.precision == BPSF_PREC_FP64, c->uniform, MODE_MAIN, true, a, pl.lds, 1, nullptr, nullptr))
     return fail(BPSF_EDEVICE, "trace launch failed");
   HIP_OK(hipDeviceSynchronize());
   HIP_OK(hipMemcpy(hard_out, dcorr.p, c->N, hipMemcpyDeviceToHost));

@@ -47,21 +47,29 @@ struct Args {
   const void* llr;           // [N] channel LLR (float or double)
   double llr_uniform;        // the common channel LLR when every prior is equal
   // problem (device)
-  const uint8_t* syndromes;  // [shots][M]
-  int64_t shots;
-  uint8_t* corrections;      // [shots][N]
+  const uint8_t* syndromes;  // [shots][syn_stride]; the first M bytes of a row are s
+  int64_t syn_stride;
+  int64_t shots;             // first-BP tasks when task_count is NULL
+  uint8_t* corrections;      // [shots][corr_stride]; the first N bytes of a row are written
+  int64_t corr_stride;
   uint8_t* converged;        // [shots]
   int32_t* iterations;       // [shots]
+  // task mapping of a launch that mixes codes (all NULL for a single code):
+  const int32_t* task_shot;  // first-BP task t -> shot
+  const unsigned long long* task_count;   // number of first-BP tasks of this code
+  int32_t* rec_list;         // i-th record of this code -> record index in the shared pool
+  unsigned long long* rec_alloc;          // allocation counter of the shared record pool
+  int D;                     // decodes per wave of this launch (1, 2, 4, 8 or 16)
   // parameters
   int max_iter, cand_max_iter, k, n_trials, select_first, flags;
   double alpha;              // > 0 fixed; 0 adaptive 1 - 2^-i
   const uint32_t* trial_masks;  // [n_trials]
   // scratch (device)
-  int32_t* records;          // [cap][rec_stride]
+  int32_t* records;          // [cap][rec_stride] (shared by the codes of a mixed launch)
   int rec_stride;
   int64_t rec_cap;
   unsigned long long* keys;  // [cap]
-  unsigned long long* counters;  // [CNT_WORDS]
+  unsigned long long* counters;  // [CNT_WORDS] of this code
   // per-iteration records of slot 0 (debug entry point only)
   void* trace_lout;          // [max_iter][N] Real
   void* trace_c2v;           // [max_iter][M*W] Real (row-major edge order)
@@ -69,5 +77,25 @@ struct Args {
 };
 
 enum : int { FLAG_NO_EARLY_STOP = 1, FLAG_FORCE_PP = 2 };
+
+// One launch over several codes: every wave starts on a code chosen in
+// proportion to the codes' estimated work and moves on to the next code when
+// that code's tasks are taken.
+constexpr int MIX_MAX_CODES = 8;
+struct MixArgs {
+  int n_codes;
+  float cost[MIX_MAX_CODES];   // relative cost of one task of the code
+  Args code[MIX_MAX_CODES];
+};
+
+// Prepass of a mixed launch: shots grouped by code into per-code task lists.
+struct BucketArgs {
+  const int32_t* shot_code;    // [shots] index of each shot's code
+  int64_t shots;
+  int n_codes;
+  int32_t* lists;              // [n_codes][shots]
+  unsigned long long* counts[MIX_MAX_CODES];   // per code: number of listed shots
+  unsigned long long* bad;     // shots whose code index is out of range
+};
 
 }  // namespace bpsf

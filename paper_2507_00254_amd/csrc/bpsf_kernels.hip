@@ -8,15 +8,18 @@
 // successful trial index ("first valid codeword").
 //
 // Execution model (one wavefront = one workgroup, persistent):
-//   * a wave runs D independent decodes ("slots"); the G = 64/D lanes of slot
-//     d are contiguous, and lane (d, q) owns checks c = q + G*k (k < IC) and
-//     bits v = q + G*k (k < IV) of that slot;
+//   * a wave runs D independent decodes ("slots"; D chosen per launch); the
+//     G = 64/D lanes of slot d are contiguous, and lane (d, q) owns the block
+//     of checks c = q*IC + k (k < IC) and the bits v = q + G*k (k < IV) of
+//     that slot, IC and IV being fixed per kernel family;
 //   * one message per Tanner edge lives in LDS: the v2c value after the bit
 //     phase and the c2v value after the check phase (each phase overwrites the
 //     edges it owns in place); layout [edge position j][slot d][check c] with
-//     stride MS per slot and CI = D*MS per position, so check-phase accesses
-//     are consecutive words and bit-phase gathers are mostly consecutive on
-//     quasi-cyclic codes;
+//     stride MS = G*IC per slot and CI = 64*IC per position. A lane's check
+//     items then sit at IC*lane + k whatever D is: compile-time offsets, and
+//     with IC odd the 32 lanes of a half-wave hit distinct banks. Bit-phase
+//     gathers of consecutive bits are mostly consecutive on quasi-cyclic
+//     codes;
 //   * the syndrome test is incremental: u = H e (one LDS word per check, laid
 //     out like the check items, bit 0 used) is toggled only when a hard
 //     decision flips, and a slot has converged when u equals its syndrome; a
@@ -91,17 +94,18 @@ __device__ __forceinline__ long long bcast0ll(long long x) {
   return ((long long)hi << 32) | (unsigned int)lo;
 }
 
-// Butterfly reductions over the G contiguous lanes of a slot. Steps inside a
-// row of 16 lanes use DPP lane permutations (no LDS traffic).
-template <int G, class Op>
-__device__ __forceinline__ uint32_t group_reduce(uint32_t x, Op op)
+// Butterfly reductions over the G contiguous lanes of a slot (G a power of
+// two, the same in every lane). Steps inside a row of 16 lanes use DPP lane
+// permutations (no LDS traffic).
+template <class Op>
+__device__ __forceinline__ uint32_t group_reduce(uint32_t x, int G, Op op)
 {
-  if constexpr (G >= 2) x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false));  // lane ^ 1
-  if constexpr (G >= 4) x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false));  // lane ^ 2
-  if constexpr (G >= 8) x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false)); // mirror in 8
-  if constexpr (G >= 16) x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xF, 0xF, false)); // mirror in 16
-  if constexpr (G >= 32) x = op(x, (uint32_t)__shfl_xor((int)x, 16));
-  if constexpr (G >= 64) x = op(x, (uint32_t)__shfl_xor((int)x, 32));
+  if (G >= 2) x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false));  // lane ^ 1
+  if (G >= 4) x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false));  // lane ^ 2
+  if (G >= 8) x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false)); // mirror in 8
+  if (G >= 16) x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xF, 0xF, false)); // mirror in 16
+  if (G >= 32) x = op(x, (uint32_t)__shfl_xor((int)x, 16));
+  if (G >= 64) x = op(x, (uint32_t)__shfl_xor((int)x, 32));
   return x;
 }
 
@@ -110,24 +114,31 @@ struct OpMax { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { re
 
 // --------------------------------------------------------------- kernel --
 
-// UL: every bit has the same channel LLR (uniform priors), held in a scalar.
-template <typename Real, int D, int IC, int IV, int W, int DV, bool UL, int MODE, bool TRACE>
-__global__ __launch_bounds__(64) void bpsf_kernel(Args a)
+// One phase (MODE) of one code: the wave takes the code's tasks until none is
+// left and returns once its slots have drained. UL: every bit has the same
+// channel LLR (uniform priors), held in a scalar.
+template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE, bool TRACE>
+__device__ __forceinline__ void decode_code(const Args& a)
 {
-  using T = TileShape<D, IC, IV, W, DV>;
+  using F = Family<IC, IV, W, DV>;
   using R = RT<Real>;
-  constexpr int G = T::G, LG = T::LG, RING = T::RING, PL = T::PL, META = T::META;
-  constexpr int KMAX = T::KMAX, MS = T::MS, CI = T::CI, MSB = T::MSB;
-  static_assert(IC <= 16, "check items are packed into 16-bit column masks");
+  constexpr int PL = F::PL, META = F::META, KMAX = F::KMAX, CI = F::CI;
+  // launch geometry (uniform)
+  const int D = a.D;
+  const int LG = 6 - __builtin_ctz((unsigned)D);   // log2 of the lanes per slot
+  const int G = 1 << LG;
+  const int MS = G * IC;                           // message entries per slot and edge position
+  const int RING = 2 * D;                          // prefetched tasks (a power of two)
 
   extern __shared__ __align__(16) unsigned char smem[];
-  const LdsLayout lay = lds_layout(sizeof(Real), W, CI, CI, a.N, DV, RING, META, KMAX, G);
+  const LdsLayout lay = lds_layout(sizeof(Real), W, CI, a.M, a.N, DV, D, UL, META);
   Real* msg = reinterpret_cast<Real*>(smem + lay.msg);
   uint32_t* uw = reinterpret_cast<uint32_t*>(smem + lay.resid);
   uint16_t* chk = reinterpret_cast<uint16_t*>(smem + lay.chk);
+  Real* lrow = reinterpret_cast<Real*>(smem + lay.lrow);
   int32_t* ring_meta = reinterpret_cast<int32_t*>(smem + lay.ring_meta);
   uint32_t* ring_syn = reinterpret_cast<uint32_t*>(smem + lay.ring_syn);
-  uint32_t* ring_tb = reinterpret_cast<uint32_t*>(smem + lay.ring_tv);
+  uint32_t* ring_tb = reinterpret_cast<uint32_t*>(smem + lay.ring_tb);
 
   const int lane = threadIdx.x;
   const int d = lane >> LG;          // slot
@@ -139,8 +150,18 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
   const Real alpha_fixed = R::from_double(adaptive ? 1.0 : a.alpha);
 
   // ---- per-code tables into LDS ------------------------------------------
+  __syncthreads();   // a previous code's phase may still be reading them
   for (int i = lane; i < N * DV; i += 64) chk[i] = a.var_chk[i];
   for (int i = lane; i < CI; i += 64) uw[i] = 0u;
+  if constexpr (!UL) {
+    // channel LLR of the bit on every edge (check c, position j): the value a
+    // fresh decode's v2c takes there
+    for (int i = lane; i < W * M; i += 64) {
+      const int j = i / M, c = i - j * M;
+      const int v = a.ell_col[c * W + j];
+      lrow[i] = v >= 0 ? llr[v] : (Real)0;
+    }
+  }
 
   // ---- per-lane constants -------------------------------------------------
   // bit items: channel LLR and the byte offsets of their DV edges
@@ -167,23 +188,7 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
     }
   }
   if constexpr (UL) Lv[0] = Lu;
-  const int cbase = d * MS + q;      // check items: entry of position 0, item 0
-
-  // message reset: a fresh decode starts from c2v = 0, i.e. v2c = L of the
-  // edge's bit. Lane i covers entries c = i + 64 h (h < MSB) of every edge
-  // position of a slot; with non-uniform priors it keeps the values to write.
-  Real rst_val[UL ? 1 : W][UL ? 1 : MSB];
-  if constexpr (!UL) {
-#pragma unroll
-    for (int j = 0; j < W; ++j)
-#pragma unroll
-      for (int h = 0; h < MSB; ++h) {
-        const int c = lane + 64 * h;
-        int v = -1;
-        if (c < M) v = a.ell_col[c * W + j];
-        rst_val[j][h] = v >= 0 ? llr[v] : (Real)0;
-      }
-  }
+  const int cbase = d * MS + q * IC;   // check items: entry of position 0, item 0 (= IC * lane)
 
   // ---- slot state (uniform over the G lanes of a slot) --------------------
   bool active = false;
@@ -205,7 +210,7 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
   long long n_tasks;
   unsigned long long* next_ctr;
   if constexpr (MODE == MODE_MAIN) {
-    n_tasks = a.shots;
+    n_tasks = a.task_count ? (long long)__atomic_load_n(a.task_count, __ATOMIC_RELAXED) : a.shots;
     next_ctr = &a.counters[CNT_MAIN_NEXT];
   } else if constexpr (MODE == MODE_CAND) {
     n_tasks = (long long)__atomic_load_n(&a.counters[CNT_FAILED], __ATOMIC_RELAXED) * a.n_trials;
@@ -228,6 +233,7 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
   uint32_t pf_tw[KMAX];                   // CAND/EMIT: my share of every Phi column
   uint32_t pf_mask = 0;
   int pf_shot = 0, pf_miters = 0, pf_f = 0, pf_ti = 0;
+  long long pf_shot_main = 0;             // MAIN: the shot of my pending task
   unsigned long long pf_key = KEY_NONE;
 #pragma unroll
   for (int k = 0; k < IC; ++k) pf_b[k] = 0;
@@ -252,10 +258,11 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
     if (d >= pend_n) return;
     const long long t = pend_base + d;
     if constexpr (MODE == MODE_MAIN) {
-      const uint8_t* s = a.syndromes + t * (long long)M;
+      pf_shot_main = a.task_shot ? (long long)a.task_shot[t] : t;
+      const uint8_t* s = a.syndromes + pf_shot_main * a.syn_stride;
 #pragma unroll
       for (int k = 0; k < IC; ++k) {
-        const int c = q + G * k;
+        const int c = q * IC + k;
         pf_b[k] = c < M ? (uint32_t)s[c] : 0u;
       }
     } else {
@@ -265,6 +272,9 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
         ti = t - f * a.n_trials;
       } else {
         f = t;
+      }
+      if (a.rec_list) f = a.rec_list[f];   // this code's f-th record in the shared pool
+      if constexpr (MODE == MODE_EMIT) {
         pf_key = a.keys[f];
         ti = pf_key == KEY_NONE ? 0 : (long long)((pf_key >> KEY_ITER_BITS) & 0xffffffffull);
       }
@@ -291,16 +301,15 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
     const int rank = __popcll(vb & ((1ull << (d * G)) - 1ull));
     const int nvalid = __popcll(vb);
     if (valid) {
-      const int e = (tail + rank) % RING;
+      const int e = (tail + rank) & (RING - 1);
       if constexpr (MODE == MODE_MAIN) {
         uint32_t bits = 0;
 #pragma unroll
         for (int k = 0; k < IC; ++k) bits |= (pf_b[k] & 1u) << k;
         ring_syn[e * G + q] = bits;
         if (q == 0) {
-          const long long t = pend_base + d;
-          ring_meta[e * META + 0] = (int32_t)(t & 0xffffffff);
-          ring_meta[e * META + 1] = (int32_t)(t >> 32);
+          ring_meta[e * META + 0] = (int32_t)(pf_shot_main & 0xffffffff);
+          ring_meta[e * META + 1] = (int32_t)(pf_shot_main >> 32);
         }
       } else {
         // s' = s + t H^T on my checks, and t on my bits
@@ -334,7 +343,7 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
     const int avail = tail - head;
     const int rank = __popcll(wb & ((1ull << (d * G)) - 1ull));
     const bool take = want && rank < avail;
-    const int e = (head + rank) % RING;
+    const int e = (head + rank) & (RING - 1);
     const int nw = __popcll(wb);
     head += nw < avail ? nw : avail;
     if (want) active = false;
@@ -355,20 +364,20 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
         main_iters = ring_meta[e * META + 4];
       }
     }
-    // messages of taken slots: v2c = L (c2v = 0 before the first iteration)
+    // messages of taken slots: v2c = L (c2v = 0 before the first iteration);
+    // the whole wave writes one slot at a time
     unsigned long long tb = __ballot(take && q == 0);
     while (tb) {
       const int ld = __ffsll((long long)tb) - 1;
       tb &= tb - 1ull;
-      const int sbase = (ld >> LG) * MS + lane;
+      const int sbase = (ld >> LG) * MS;
+      for (int c = lane; c < MS; c += 64) {
 #pragma unroll
-      for (int j = 0; j < W; ++j)
-#pragma unroll
-        for (int h = 0; h < MSB; ++h)
-          if (64 * h + lane < MS) {
-            if constexpr (UL) msg[j * CI + sbase + 64 * h] = Lu;
-            else msg[j * CI + sbase + 64 * h] = rst_val[j][h];
-          }
+        for (int j = 0; j < W; ++j) {
+          if constexpr (UL) msg[j * CI + sbase + c] = Lu;
+          else msg[j * CI + sbase + c] = c < M ? lrow[j * M + c] : (Real)0;
+        }
+      }
     }
   };
 
@@ -399,7 +408,7 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
         Real (&xc)[W] = x[k & 1];
         if (k + 1 < IC) {
 #pragma unroll
-          for (int j = 0; j < W; ++j) x[(k + 1) & 1][j] = msg[j * CI + cbase + G * (k + 1)];
+          for (int j = 0; j < W; ++j) x[(k + 1) & 1][j] = msg[j * CI + cbase + k + 1];
         }
         Real m1 = R::minr(R::absr(xc[0]), R::absr(xc[1]));
         Real m2 = R::maxr(R::absr(xc[0]), R::absr(xc[1]));
@@ -418,9 +427,9 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
         for (int j = 0; j < W; ++j) {
           // the minimum over the other edges: min2 on the edge holding min1
           const Real o = R::flip(R::absr(xc[j]) == m1 ? s2 : s1, R::sw(xc[j]));
-          msg[j * CI + cbase + G * k] = o;
+          msg[j * CI + cbase + k] = o;
           if constexpr (TRACE) {
-            const int c = q + G * k;
+            const int c = q * IC + k;
             if (d == 0 && active && c < M)
               reinterpret_cast<Real*>(a.trace_c2v)[(long long)iter * M * W + c * W + j] = o;
           }
@@ -491,7 +500,7 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
     // ---- syndrome test of every slot: u == s on all its checks ----
     uint32_t un = 0;
 #pragma unroll
-    for (int k = 0; k < IC; ++k) un |= uw[cbase + G * k] ^ (synbits >> k);
+    for (int k = 0; k < IC; ++k) un |= uw[cbase + k] ^ (synbits >> k);
     un &= 1u;
     const unsigned long long ub = __ballot(un != 0u);
     const unsigned long long gm = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
@@ -502,12 +511,17 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
     const bool fin = active && (stop_ok || iter >= cap);
 
     if (__ballot(fin) != 0ull) {
+      // G through an opaque copy: keeps the compiler from hoisting the bit
+      // offsets q + G*k of every item out of the main loop (registers held
+      // across the whole decode otherwise)
+      int Gf = G;
+      asm volatile("" : "+s"(Gf));
       if constexpr (MODE == MODE_MAIN) {
         if (fin) {
-          uint8_t* out = a.corrections + shot * (long long)N;
+          uint8_t* out = a.corrections + shot * a.corr_stride;
 #pragma unroll
           for (int k = 0; k < IV; ++k)
-            if ((vmask >> k) & 1u) out[q + G * k] = (uint8_t)((hb >> k) & 1u);
+            if ((vmask >> k) & 1u) out[q + Gf * k] = (uint8_t)((hb >> k) & 1u);
           if (q == 0) {
             a.converged[shot] = (uint8_t)conv;
             a.iterations[shot] = iter;
@@ -524,10 +538,17 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
             uint32_t cn = 0;
 #pragma unroll
             for (int b = 0; b < PL; ++b) cn |= ((cnt[b] >> k) & 1u) << b;
-            key[k] = ((vmask >> k) & 1u) ? ((cn << 16) | (uint32_t)(0xffff - (q + G * k))) : 0u;
+            key[k] = ((vmask >> k) & 1u) ? ((cn << 16) | (uint32_t)(0xffff - (q + Gf * k))) : 0u;
           }
           int f = 0;
-          if (need && q == 0) f = (int)atomicAdd(&a.counters[CNT_FAILED], 1ull);
+          if (need && q == 0) {
+            f = (int)atomicAdd(&a.counters[CNT_FAILED], 1ull);
+            if (a.rec_list) {
+              const int i = f;
+              f = (int)atomicAdd(a.rec_alloc, 1ull);
+              a.rec_list[i] = f;
+            }
+          }
           f = __shfl(f, d * G);
           int32_t* r = a.records + (long long)f * rstride;
           if (need) {
@@ -544,14 +565,15 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
             uint32_t best = 0;
 #pragma unroll
             for (int k = 0; k < IV; ++k) best = key[k] > best ? key[k] : best;
-            best = group_reduce<G>(best, OpMax());
+            best = group_reduce(best, G, OpMax());
             const int v = best ? 0xffff - (int)(best & 0xffffu) : 0;   // best > 0 while k <= N
             // my share of column v: my checks among its DV checks, and v itself
             uint32_t tw = 0;
 #pragma unroll
             for (int i = 0; i < DV; ++i) {
               const int c = chk[v * DV + i];
-              if ((c & (G - 1)) == q) tw ^= 1u << (c >> LG);
+              const int owner = c / IC;
+              if (owner == q) tw ^= 1u << (c - owner * IC);
             }
             if ((v & (G - 1)) == q) tw |= (uint32_t)((v >> LG) + 1) << 16;
             if (need) {
@@ -561,13 +583,13 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
             if ((v & (G - 1)) == q) {
 #pragma unroll
               for (int k = 0; k < IV; ++k)
-                if (q + G * k == v) key[k] = 0u;
+                if (q + Gf * k == v) key[k] = 0u;
             }
           }
         }
       } else if constexpr (MODE == MODE_CAND) {
         // weight of the undone correction e = e' + t over the slot
-        const uint32_t w = group_reduce<G>((uint32_t)__popc((hb ^ tbits) & vmask), OpAdd());
+        const uint32_t w = group_reduce((uint32_t)__popc((hb ^ tbits) & vmask), G, OpAdd());
         if (fin && q == 0) {
           st_iters += (unsigned long long)iter;
           if (conv) {
@@ -581,11 +603,11 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
         }
       } else {  // MODE_EMIT
         if (fin) {
-          uint8_t* out = a.corrections + shot * (long long)N;
+          uint8_t* out = a.corrections + shot * a.corr_stride;
           const uint32_t e = hb ^ tbits;
 #pragma unroll
           for (int k = 0; k < IV; ++k)
-            if ((vmask >> k) & 1u) out[q + G * k] = (uint8_t)((e >> k) & 1u);
+            if ((vmask >> k) & 1u) out[q + Gf * k] = (uint8_t)((e >> k) & 1u);
           if (q == 0) {
             a.converged[shot] = 1;
             a.iterations[shot] = main_iters + iter;
@@ -609,71 +631,193 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
   if (lane == 0) atomicAdd(&a.counters[ST_WAVES], 1ull);
 }
 
-__global__ void bpsf_reset_counters(unsigned long long* c)
+template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE, bool TRACE>
+__global__ __launch_bounds__(64) void bpsf_kernel(Args a)
 {
-  if (threadIdx.x < CNT_WORDS) c[threadIdx.x] = 0ull;
+  decode_code<Real, IC, IV, W, DV, UL, MODE, TRACE>(a);
+}
+
+// ------------------------------------------------------- mixed launches --
+
+// Tasks of a phase of one code (as decode_code counts them).
+template <int MODE>
+__device__ __forceinline__ long long phase_tasks(const Args& a)
+{
+  if constexpr (MODE == MODE_MAIN)
+    return a.task_count ? (long long)__atomic_load_n(a.task_count, __ATOMIC_RELAXED) : a.shots;
+  const long long f = (long long)__atomic_load_n(&a.counters[CNT_FAILED], __ATOMIC_RELAXED);
+  return MODE == MODE_CAND ? f * a.n_trials : f;
+}
+
+// One phase over several codes of one family: every wave starts on the code
+// under the point (b + 1/2) / grid of the cumulative estimated work and then
+// takes the codes after it in turn, so waves whose code runs out help the
+// others.
+template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE>
+__global__ __launch_bounds__(64) void bpsf_mixed_kernel(const MixArgs* __restrict__ mp)
+{
+  const MixArgs& m = *mp;   // device copy written by the host before the launch
+  float w[MIX_MAX_CODES];
+  float total = 0.f;
+  for (int c = 0; c < m.n_codes; ++c) {
+    w[c] = (float)phase_tasks<MODE>(m.code[c]) * m.cost[c];
+    total += w[c];
+  }
+  const float at = ((float)blockIdx.x + 0.5f) / (float)gridDim.x * total;
+  int c0 = 0;
+  float acc = 0.f;
+  for (int c = 0; c < m.n_codes; ++c) {
+    if (w[c] <= 0.f) continue;
+    c0 = c;
+    acc += w[c];
+    if (at < acc) break;
+  }
+  c0 = __builtin_amdgcn_readfirstlane(c0);
+  for (int i = 0; i < m.n_codes; ++i) {
+    const int c = (c0 + i) % m.n_codes;
+    decode_code<Real, IC, IV, W, DV, UL, MODE, false>(m.code[c]);
+  }
+}
+
+__global__ void bpsf_bucket_kernel(BucketArgs b)
+{
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  int c = -1;
+  if (i < b.shots) {
+    c = b.shot_code[i];
+    if (c < 0 || c >= b.n_codes) {
+      atomicAdd(b.bad, 1ull);
+      c = -1;
+    }
+  }
+  // one counter update per (wave, code)
+  for (int cc = 0; cc < b.n_codes; ++cc) {
+    const unsigned long long mine = __ballot(c == cc);
+    if (mine == 0ull) continue;
+    const int leader = __ffsll((long long)mine) - 1;
+    unsigned long long base = 0;
+    if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(b.counts[cc], (unsigned long long)__popcll(mine));
+    base = __shfl(base, leader);
+    if (c == cc) {
+      const int rank = __popcll(mine & ((1ull << (threadIdx.x & 63)) - 1ull));
+      b.lists[(long long)cc * b.shots + (long long)(base + rank)] = (int32_t)i;
+    }
+  }
+}
+
+__global__ void bpsf_reset_counters(unsigned long long* c, int n)
+{
+  for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0ull;
 }
 
 // ------------------------------------------------------------ dispatch --
 
-template <typename Real, int D, int IC, int IV, int W, int DV, bool UL>
-static int launch_tile(int mode, bool trace, const Args& a, int grid, void* stream)
+template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE, bool TRACE>
+static int run_kernel(int what, const Args& a, size_t lds, int grid, hipStream_t st, int* out)
 {
-  using T = TileShape<D, IC, IV, W, DV>;
-  const LdsLayout lay = lds_layout(sizeof(Real), W, T::CI, T::CI, a.N, DV, T::RING, T::META, T::KMAX, T::G);
-  const size_t sh = lay.total;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (mode == MODE_MAIN && trace)
-    hipLaunchKernelGGL((bpsf_kernel<Real, D, IC, IV, W, DV, UL, MODE_MAIN, true>), dim3(grid), dim3(64), sh, st, a);
-  else if (mode == MODE_MAIN)
-    hipLaunchKernelGGL((bpsf_kernel<Real, D, IC, IV, W, DV, UL, MODE_MAIN, false>), dim3(grid), dim3(64), sh, st, a);
-  else if (mode == MODE_CAND)
-    hipLaunchKernelGGL((bpsf_kernel<Real, D, IC, IV, W, DV, UL, MODE_CAND, false>), dim3(grid), dim3(64), sh, st, a);
-  else
-    hipLaunchKernelGGL((bpsf_kernel<Real, D, IC, IV, W, DV, UL, MODE_EMIT, false>), dim3(grid), dim3(64), sh, st, a);
+  if (what == 1)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bpsf_kernel<Real, IC, IV, W, DV, UL, MODE, TRACE>, 64,
+                                                        lds) == hipSuccess ? 0 : -1;
+  hipLaunchKernelGGL((bpsf_kernel<Real, IC, IV, W, DV, UL, MODE, TRACE>), dim3(grid), dim3(64), lds, st, a);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <typename Real, int D, int IC, int IV, int W, int DV, bool UL>
-static int occupancy_tile(int mode, const Args& a, int* blocks_per_cu)
+template <typename Real, int IC, int IV, int W, int DV, bool UL>
+static int run_mode(int what, int mode, bool trace, const Args& a, size_t lds, int grid, hipStream_t st, int* out)
 {
-  using T = TileShape<D, IC, IV, W, DV>;
-  const LdsLayout lay = lds_layout(sizeof(Real), W, T::CI, T::CI, a.N, DV, T::RING, T::META, T::KMAX, T::G);
-  hipError_t e;
   if (mode == MODE_MAIN)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, bpsf_kernel<Real, D, IC, IV, W, DV, UL, MODE_MAIN, false>, 64, lay.total);
-  else if (mode == MODE_CAND)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, bpsf_kernel<Real, D, IC, IV, W, DV, UL, MODE_CAND, false>, 64, lay.total);
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, bpsf_kernel<Real, D, IC, IV, W, DV, UL, MODE_EMIT, false>, 64, lay.total);
-  return e == hipSuccess ? 0 : -1;
+    return trace ? run_kernel<Real, IC, IV, W, DV, UL, MODE_MAIN, true>(what, a, lds, grid, st, out)
+                 : run_kernel<Real, IC, IV, W, DV, UL, MODE_MAIN, false>(what, a, lds, grid, st, out);
+  if (mode == MODE_CAND) return run_kernel<Real, IC, IV, W, DV, UL, MODE_CAND, false>(what, a, lds, grid, st, out);
+  return run_kernel<Real, IC, IV, W, DV, UL, MODE_EMIT, false>(what, a, lds, grid, st, out);
 }
 
-template <typename Real, int D, int IC, int IV, int W, int DV>
-static int tile_call(int what, bool ul, int mode, bool trace, const Args& a, int grid, void* st, int* out)
+template <typename Real, int IC, int IV, int W, int DV, bool UL>
+static int run_mixed(int what, int mode, const MixArgs* m, size_t lds, int grid, hipStream_t st, int* out)
 {
-  if (ul) return what == 0 ? launch_tile<Real, D, IC, IV, W, DV, true>(mode, trace, a, grid, st)
-                            : occupancy_tile<Real, D, IC, IV, W, DV, true>(mode, a, out);
-  return what == 0 ? launch_tile<Real, D, IC, IV, W, DV, false>(mode, trace, a, grid, st)
-                   : occupancy_tile<Real, D, IC, IV, W, DV, false>(mode, a, out);
-}
-
-#define BPSF_TILE_CASE(D_, IC_, IV_, W_, DV_)                                                          \
-  if (t.D == D_ && t.IC == IC_ && t.IV == IV_ && t.W == W_ && t.DV == DV_) {                           \
-    return fp64 ? tile_call<double, D_, IC_, IV_, W_, DV_>(what, ul, mode, trace, a, grid, st, out)    \
-                : tile_call<float, D_, IC_, IV_, W_, DV_>(what, ul, mode, trace, a, grid, st, out);    \
+  if (what == 1) {
+    hipError_t e;
+    if (mode == MODE_MAIN)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bpsf_mixed_kernel<Real, IC, IV, W, DV, UL, MODE_MAIN>, 64, lds);
+    else if (mode == MODE_CAND)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bpsf_mixed_kernel<Real, IC, IV, W, DV, UL, MODE_CAND>, 64, lds);
+    else
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bpsf_mixed_kernel<Real, IC, IV, W, DV, UL, MODE_EMIT>, 64, lds);
+    return e == hipSuccess ? 0 : -1;
   }
-
-int tile_dispatch(int what, const TileDesc& t, bool fp64, bool ul, int mode, bool trace, const Args& a, int grid,
-                  void* st, int* out)
-{
-  BPSF_TILE_LIST(BPSF_TILE_CASE)
-  return -2;   // no such tile compiled
+  if (mode == MODE_MAIN)
+    hipLaunchKernelGGL((bpsf_mixed_kernel<Real, IC, IV, W, DV, UL, MODE_MAIN>), dim3(grid), dim3(64), lds, st, m);
+  else if (mode == MODE_CAND)
+    hipLaunchKernelGGL((bpsf_mixed_kernel<Real, IC, IV, W, DV, UL, MODE_CAND>), dim3(grid), dim3(64), lds, st, m);
+  else
+    hipLaunchKernelGGL((bpsf_mixed_kernel<Real, IC, IV, W, DV, UL, MODE_EMIT>), dim3(grid), dim3(64), lds, st, m);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int reset_counters(unsigned long long* c, void* stream)
+int family_count()
 {
-  hipLaunchKernelGGL(bpsf_reset_counters, dim3(1), dim3(64), 0, reinterpret_cast<hipStream_t>(stream), c);
+  int n = 0;
+#define BPSF_FAMILY_COUNT(IC_, IV_, W_, DV_) ++n;
+  BPSF_FAMILY_LIST(BPSF_FAMILY_COUNT)
+#undef BPSF_FAMILY_COUNT
+  return n;
+}
+
+FamilyDesc family_desc(int fam)
+{
+  int i = 0;
+#define BPSF_FAMILY_DESC(IC_, IV_, W_, DV_) \
+  if (i++ == fam) return FamilyDesc{IC_, IV_, W_, DV_};
+  BPSF_FAMILY_LIST(BPSF_FAMILY_DESC)
+#undef BPSF_FAMILY_DESC
+  return FamilyDesc{0, 0, 0, 0};
+}
+
+int tile_dispatch(int what, const TileDesc& t, bool fp64, bool ul, int mode, bool trace, const Args& a, size_t lds,
+                  int grid, void* stream, int* out)
+{
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int i = 0;
+#define BPSF_FAMILY_CASE(IC_, IV_, W_, DV_)                                                                 \
+  if (i++ == t.fam) {                                                                                       \
+    if (fp64) return ul ? run_mode<double, IC_, IV_, W_, DV_, true>(what, mode, trace, a, lds, grid, st, out) \
+                        : run_mode<double, IC_, IV_, W_, DV_, false>(what, mode, trace, a, lds, grid, st, out); \
+    return ul ? run_mode<float, IC_, IV_, W_, DV_, true>(what, mode, trace, a, lds, grid, st, out)            \
+              : run_mode<float, IC_, IV_, W_, DV_, false>(what, mode, trace, a, lds, grid, st, out);          \
+  }
+  BPSF_FAMILY_LIST(BPSF_FAMILY_CASE)
+#undef BPSF_FAMILY_CASE
+  return -2;   // no such family compiled
+}
+
+int mixed_dispatch(int what, int fam, bool fp64, bool ul, int mode, const MixArgs* m, size_t lds, int grid,
+                   void* stream, int* out)
+{
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int i = 0;
+#define BPSF_FAMILY_MIX(IC_, IV_, W_, DV_)                                                        \
+  if (i++ == fam) {                                                                               \
+    if (fp64) return ul ? run_mixed<double, IC_, IV_, W_, DV_, true>(what, mode, m, lds, grid, st, out) \
+                        : run_mixed<double, IC_, IV_, W_, DV_, false>(what, mode, m, lds, grid, st, out); \
+    return ul ? run_mixed<float, IC_, IV_, W_, DV_, true>(what, mode, m, lds, grid, st, out)            \
+              : run_mixed<float, IC_, IV_, W_, DV_, false>(what, mode, m, lds, grid, st, out);          \
+  }
+  BPSF_FAMILY_LIST(BPSF_FAMILY_MIX)
+#undef BPSF_FAMILY_MIX
+  return -2;
+}
+
+int bucket_launch(const BucketArgs& b, void* stream)
+{
+  if (b.shots <= 0) return 0;
+  const long long blocks = (b.shots + 255) / 256;
+  hipLaunchKernelGGL(bpsf_bucket_kernel, dim3((unsigned)blocks), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), b);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int reset_counters(unsigned long long* c, int n, void* stream)
+{
+  hipLaunchKernelGGL(bpsf_reset_counters, dim3(1), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), c, n);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
