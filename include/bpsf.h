@@ -150,6 +150,49 @@ int64_t bpsf_num_trials(const bpsf_params* params, uint32_t* masks_out, int64_t 
 int bpsf_set_timing(bpsf_code code, int enable);
 int bpsf_last_timing(bpsf_code code, float* ms_out);
 
+/*
+ * Decoding shots of several codes in one go. A mix handle names up to 8
+ * loaded codes (distinct handles on one device that share a kernel family:
+ * equal row and column weights, as the bivariate-bicycle codes of Appendix A
+ * do; otherwise BPSF_ENOTSUP). It owns a scratch area of its own; the codes
+ * must outlive it and keep their tables, but their LLR and trial tables are
+ * refreshed by every bpsf_mix_decode, so calls on a mix and on its codes must
+ * be ordered (one stream). bpsf_mix_free waits for the device.
+ */
+typedef struct bpsf_mix_s* bpsf_mix;
+int bpsf_mix_create(const bpsf_code* codes, int32_t n_codes, bpsf_mix* out);
+void bpsf_mix_free(bpsf_mix mix);
+
+/*
+ * Decode `shots` shots, shot i being a syndrome of codes[shot_code[i]]. Every
+ * decode phase of Algorithm 1 (first BP, trial BPs, re-runs of the winners)
+ * is one persistent launch over all codes: a wave takes decodes of one code
+ * at a time and moves to another code once that one's work is taken, so the
+ * codes share one tail instead of one each. Each shot's result is what
+ * bpsf_decode returns for it alone with the same priors and parameters.
+ *   shot_code    device, int32 [shots], entries in [0, n_codes); shots with
+ *                other entries are skipped (outputs untouched) and counted
+ *                in bpsf_mix_last_stats's *invalid_shots
+ *   syndromes    device, uint8 [shots][syn_stride]; row i holds s_i in its
+ *                first M bytes of its code (syn_stride >= every M)
+ *   priors       host, priors[c] -> double [N of code c], as for bpsf_decode
+ *   params       host, shared by every code
+ *   corrections  device, uint8 [shots][corr_stride]; the first N bytes of
+ *                row i are written (corr_stride >= every N)
+ *   converged, iterations   device [shots], as for bpsf_decode
+ * Scratch: 8 * n_codes + 4 + 4 * (rec words) bytes per shot, grown as
+ * needed and reused.
+ */
+int bpsf_mix_decode(bpsf_mix mix, const int32_t* shot_code, const uint8_t* syndromes, int64_t syn_stride,
+                    const double* const* priors, int64_t shots, const bpsf_params* params,
+                    uint8_t* corrections, int64_t corr_stride, uint8_t* converged, int32_t* iterations,
+                    void* stream);
+
+/* Work counters of the last bpsf_mix_decode, per code (host out [n_codes]),
+ * and the number of shots whose code index was out of range (may be NULL).
+ * Waits for `stream`. */
+int bpsf_mix_last_stats(bpsf_mix mix, void* stream, bpsf_stats* per_code, int64_t* invalid_shots);
+
 /* Shape of a loaded code: M, N, edges, row weight, column weight (host outs, any may be NULL). */
 int bpsf_code_info(bpsf_code code, int32_t* M, int32_t* N, int32_t* edges, int32_t* row_weight,
                    int32_t* col_weight);

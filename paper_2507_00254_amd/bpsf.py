@@ -59,6 +59,11 @@ def _load():
     lib.bpsf_set_timing.argtypes = [vp, C.c_int]
     lib.bpsf_last_timing.argtypes = [vp, P(C.c_float)]
     lib.bpsf_code_info.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(i32)]
+    lib.bpsf_mix_create.argtypes = [P(vp), i32, P(vp)]
+    lib.bpsf_mix_free.argtypes = [vp]
+    lib.bpsf_mix_free.restype = None
+    lib.bpsf_mix_decode.argtypes = [vp, vp, vp, i64, P(P(C.c_double)), i64, P(bpsf_params), vp, i64, vp, vp, vp]
+    lib.bpsf_mix_last_stats.argtypes = [vp, vp, P(bpsf_stats), P(i64)]
     lib.bpsf_last_error.argtypes = []
     lib.bpsf_last_error.restype = C.c_char_p
     return lib
@@ -150,6 +155,47 @@ def bpsf_last_timing(handle) -> dict:
     ms = (C.c_float * 4)()
     _check(LIB.bpsf_last_timing(C.c_void_p(handle), ms))
     return {"total": ms[0], "main": ms[1], "trials": ms[2], "rerun": ms[3]}
+
+
+def bpsf_mix_create(handles) -> int:
+    """A mix handle over loaded codes (see bpsf_mix_decode)."""
+    arr = (C.c_void_p * len(handles))(*handles)
+    out = C.c_void_p()
+    _check(LIB.bpsf_mix_create(arr, len(handles), C.byref(out)))
+    return out.value
+
+
+def bpsf_mix_free(mix) -> None:
+    LIB.bpsf_mix_free(mix)
+
+
+def bpsf_mix_decode(mix, shot_code, syndromes, priors, params: bpsf_params, corrections, converged, iterations,
+                    stream=None) -> None:
+    """Enqueue a decode of shots of several codes. ``shot_code`` int32
+    [shots], ``syndromes`` uint8 [shots, syn_stride], ``corrections`` uint8
+    [shots, corr_stride], ``converged`` uint8 [shots], ``iterations`` int32
+    [shots] are device tensors; ``priors`` is a list of host arrays, one per
+    code of the mix."""
+    shots = int(shot_code.shape[0])
+    for t in (shot_code, syndromes, corrections, converged, iterations):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("device tensors must be contiguous CUDA (HIP) tensors")
+    pri = [np.ascontiguousarray(x, dtype=np.float64) for x in priors]
+    parr = (C.POINTER(C.c_double) * len(pri))(*[x.ctypes.data_as(C.POINTER(C.c_double)) for x in pri])
+    _check(LIB.bpsf_mix_decode(C.c_void_p(mix), C.c_void_p(shot_code.data_ptr()), C.c_void_p(syndromes.data_ptr()),
+                               int(syndromes.shape[1]), parr, shots, C.byref(params),
+                               C.c_void_p(corrections.data_ptr()), int(corrections.shape[1]),
+                               C.c_void_p(converged.data_ptr()), C.c_void_p(iterations.data_ptr()),
+                               _stream_ptr(stream)))
+
+
+def bpsf_mix_last_stats(mix, n_codes: int, stream=None):
+    """Per-code work counters of the last mixed decode and the number of
+    shots skipped for an out-of-range code index."""
+    st = (bpsf_stats * n_codes)()
+    bad = C.c_int64()
+    _check(LIB.bpsf_mix_last_stats(C.c_void_p(mix), _stream_ptr(stream), st, C.byref(bad)))
+    return [{f: getattr(x, f) for f, _ in bpsf_stats._fields_} for x in st], bad.value
 
 
 def bpsf_code_info(handle) -> dict:

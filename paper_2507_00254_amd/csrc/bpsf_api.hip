@@ -118,10 +118,10 @@ int pick_tile(const bpsf_code_s* c, TileDesc* out)
   return -1;
 }
 
-size_t tile_lds(const bpsf_code_s* c, const TileDesc& t, bool fp64)
+size_t tile_lds(const bpsf_code_s* c, const TileDesc& t, bool fp64, bool uniform)
 {
   const FamilyDesc f = family_desc(t.fam);
-  return lds_layout(fp64 ? 8 : 4, f.W, 64 * f.IC, c->M, c->N, f.DV, t.D, c->uniform, 8).total;
+  return lds_layout(fp64 ? 8 : 4, f.W, 64 * f.IC, c->M, c->N, f.DV, t.D, uniform, 8).total;
 }
 
 // Trial vectors of Algorithm 1 as k-bit masks over Phi, in trial order.
@@ -219,13 +219,13 @@ struct Plan {
   int grid[3];
 };
 
-int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
+// Code, geometry and parameter fields of a launch's Args (no problem
+// buffers, no scratch).
+int fill_code_args(const bpsf_code_s* c, const bpsf_params* p, const TileDesc& t, Args* out)
 {
-  if (pick_tile(c, &pl->tile)) return fail(BPSF_ENOTSUP, "no kernel tile for this code");
   if (p->k > c->N) return fail(BPSF_EINVAL, "k = %d exceeds the %d bits of the code", p->k, c->N);
-  const TileDesc& t = pl->tile;
   const int G = 64 / t.D;
-  Args& a = pl->args;
+  Args& a = *out;
   memset(&a, 0, sizeof a);
   a.M = c->M;
   a.N = c->N;
@@ -235,7 +235,6 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
   a.ell_col = static_cast<const int32_t*>(c->ell_col.p);
   a.llr = p->precision == BPSF_PREC_FP64 ? c->llr64.p : c->llr32.p;
   a.llr_uniform = c->llr_uniform;
-  a.shots = shots;
   a.syn_stride = c->M;
   a.corr_stride = c->N;
   a.max_iter = p->max_iter;
@@ -250,18 +249,29 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
   const int kk = p->k > 0 ? p->k : 1;
   a.rec_stride = REC_HDR + G * (kk + 1) + kk;
   a.chunk = 2 * t.D;
+  return 0;
+}
+
+int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
+{
+  if (pick_tile(c, &pl->tile)) return fail(BPSF_ENOTSUP, "no kernel tile for this code");
+  const TileDesc& t = pl->tile;
+  Args& a = pl->args;
+  int rc = fill_code_args(c, p, t, &a);
+  if (rc) return rc;
+  a.shots = shots;
   // scratch: one record and key per shot at most
   const int64_t cap = shots > 0 ? shots : 1;
   if (c->records.ensure(sizeof(int32_t) * (size_t)a.rec_stride * (size_t)cap) ||
       c->keys.ensure(sizeof(unsigned long long) * (size_t)cap) ||
-      c->counters.ensure(sizeof(unsigned long long) * CNT_WORDS * MIX_MAX_CODES))
+      c->counters.ensure(sizeof(unsigned long long) * CNT_WORDS))
     return fail(BPSF_ENOMEM, "scratch for %lld shots", (long long)shots);
   a.records = static_cast<int32_t*>(c->records.p);
   a.rec_cap = cap;
   a.keys = static_cast<unsigned long long*>(c->keys.p);
   a.counters = static_cast<unsigned long long*>(c->counters.p);
   const bool fp64 = p->precision == BPSF_PREC_FP64;
-  pl->lds = tile_lds(c, t, fp64);
+  pl->lds = tile_lds(c, t, fp64, c->uniform);
   for (int mode = 0; mode < 3; ++mode) {
     int per_cu = 0;
     if (tile_dispatch(1, t, fp64, c->uniform, mode, false, a, pl->lds, 0, nullptr, &per_cu) || per_cu < 1)
@@ -270,6 +280,26 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
   }
   return 0;
 }
+
+}  // namespace
+
+// Several codes decoded together (bpsf_mix_*): per-code task and record lists
+// and a record pool shared by the codes.
+struct bpsf_mix_s {
+  int n = 0;
+  bpsf_code_s* codes[MIX_MAX_CODES] = {};
+  int fam = -1;
+  DevBuf lists;      // [n][shots] int32 shot indices, grouped by code
+  DevBuf rec_lists;  // [n][shots] int32 record indices of each code
+  DevBuf records, keys;
+  DevBuf counters;   // [n][CNT_WORDS] per code, then the mix words below
+  std::mutex mu;
+};
+
+namespace {
+
+// Mix words after the per-code counter blocks.
+enum : int { MIX_TASKS = 0, MIX_REC_ALLOC = MIX_MAX_CODES, MIX_BAD = MIX_MAX_CODES + 1, MIX_WORDS = MIX_MAX_CODES + 2 };
 
 }  // namespace
 
@@ -494,6 +524,162 @@ int bpsf_bp_trace(bpsf_code c, const uint8_t* syndrome, const double* priors, co
   HIP_OK(hipMemcpy(iters_out, dit.p, 4, hipMemcpyDeviceToHost));
   if (lout_trace) HIP_OK(hipMemcpy(lout_trace, dl.p, nl, hipMemcpyDeviceToHost));
   if (c2v_trace) HIP_OK(hipMemcpy(c2v_trace, dc.p, nc, hipMemcpyDeviceToHost));
+  return 0;
+}
+
+int bpsf_mix_create(const bpsf_code* codes, int32_t n_codes, bpsf_mix* out)
+{
+  if (!out) return fail(BPSF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!codes || n_codes < 1 || n_codes > MIX_MAX_CODES)
+    return fail(BPSF_EINVAL, "need 1..%d codes", MIX_MAX_CODES);
+  int fam = -1;
+  for (int i = 0; i < n_codes; ++i) {
+    if (!codes[i]) return fail(BPSF_EINVAL, "codes[%d] is NULL", i);
+    for (int j = 0; j < i; ++j)
+      if (codes[j] == codes[i]) return fail(BPSF_EINVAL, "codes[%d] repeats codes[%d]", i, j);
+    if (codes[i]->device != codes[0]->device) return fail(BPSF_EINVAL, "codes live on different devices");
+    TileDesc t;
+    if (pick_tile(codes[i], &t)) return fail(BPSF_ENOTSUP, "codes[%d] has no kernel tile", i);
+    if (fam >= 0 && t.fam != fam)
+      return fail(BPSF_ENOTSUP, "codes[%d] needs another kernel family than codes[0]", i);
+    fam = t.fam;
+  }
+  bpsf_mix_s* m = new (std::nothrow) bpsf_mix_s;
+  if (!m) return fail(BPSF_ENOMEM, "handle");
+  m->n = n_codes;
+  for (int i = 0; i < n_codes; ++i) m->codes[i] = codes[i];
+  m->fam = fam;
+  *out = m;
+  return 0;
+}
+
+void bpsf_mix_free(bpsf_mix m)
+{
+  if (!m) return;
+  (void)hipDeviceSynchronize();
+  delete m;
+}
+
+int bpsf_mix_decode(bpsf_mix m, const int32_t* shot_code, const uint8_t* syndromes, int64_t syn_stride,
+                    const double* const* priors, int64_t shots, const bpsf_params* p, uint8_t* corrections,
+                    int64_t corr_stride, uint8_t* converged, int32_t* iterations, void* stream)
+{
+  if (!m) return fail(BPSF_EINVAL, "mix is NULL");
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (shots < 0) return fail(BPSF_EINVAL, "shots < 0");
+  if (shots > 0x7fffffffLL) return fail(BPSF_EINVAL, "at most 2^31-1 shots per call");
+  if (!priors) return fail(BPSF_EINVAL, "priors is NULL");
+  for (int i = 0; i < m->n; ++i) {
+    if (syn_stride < m->codes[i]->M) return fail(BPSF_EINVAL, "syn_stride %lld < M = %d of code %d", (long long)syn_stride, m->codes[i]->M, i);
+    if (corr_stride < m->codes[i]->N) return fail(BPSF_EINVAL, "corr_stride %lld < N = %d of code %d", (long long)corr_stride, m->codes[i]->N, i);
+  }
+  if (shots > 0 && (!shot_code || !syndromes || !corrections || !converged || !iterations))
+    return fail(BPSF_EINVAL, "NULL buffer");
+  std::lock_guard<std::mutex> lk(m->mu);
+  // the codes' LLR and trial tables (each code's own lock; a fixed order)
+  bool uniform = true;
+  for (int i = 0; i < m->n; ++i) {
+    bpsf_code_s* c = m->codes[i];
+    std::lock_guard<std::mutex> lc(c->mu);
+    if ((rc = update_llr(c, priors[i]))) return rc;
+    if ((rc = update_masks(c, p))) return rc;
+    uniform = uniform && c->uniform;
+  }
+  if (shots == 0) return 0;
+  const bool fp64 = p->precision == BPSF_PREC_FP64;
+  MixArgs ma;
+  memset(&ma, 0, sizeof ma);
+  ma.n_codes = m->n;
+  size_t lds = 0;
+  int stride = 0;
+  TileDesc tiles[MIX_MAX_CODES];
+  for (int i = 0; i < m->n; ++i) {
+    bpsf_code_s* c = m->codes[i];
+    if (pick_tile(c, &tiles[i]) || tiles[i].fam != m->fam) return fail(BPSF_ENOTSUP, "code %d changed kernel family", i);
+    if ((rc = fill_code_args(c, p, tiles[i], &ma.code[i]))) return rc;
+    // a mixed launch runs the uniform-LLR kernel only when every code qualifies
+    lds = std::max(lds, tile_lds(c, tiles[i], fp64, uniform));
+    stride = std::max(stride, ma.code[i].rec_stride);
+    ma.cost[i] = 1.0f / (float)tiles[i].D;   // a wave iteration costs the same for every D
+  }
+  // scratch
+  const size_t n = (size_t)shots;
+  const size_t words = (size_t)CNT_WORDS * m->n + MIX_WORDS;
+  if (m->lists.ensure(sizeof(int32_t) * n * m->n) || m->rec_lists.ensure(sizeof(int32_t) * n * m->n) ||
+      m->records.ensure(sizeof(int32_t) * n * (size_t)stride) || m->keys.ensure(sizeof(unsigned long long) * n) ||
+      m->counters.ensure(sizeof(unsigned long long) * words))
+    return fail(BPSF_ENOMEM, "scratch for %lld shots", (long long)shots);
+  unsigned long long* cnt = static_cast<unsigned long long*>(m->counters.p);
+  unsigned long long* mixw = cnt + (size_t)CNT_WORDS * m->n;
+  for (int i = 0; i < m->n; ++i) {
+    Args& a = ma.code[i];
+    a.syndromes = syndromes;
+    a.syn_stride = syn_stride;
+    a.shots = shots;
+    a.corrections = corrections;
+    a.corr_stride = corr_stride;
+    a.converged = converged;
+    a.iterations = iterations;
+    a.task_shot = static_cast<const int32_t*>(m->lists.p) + (size_t)i * n;
+    a.task_count = mixw + MIX_TASKS + i;
+    a.rec_list = static_cast<int32_t*>(m->rec_lists.p) + (size_t)i * n;
+    a.rec_alloc = mixw + MIX_REC_ALLOC;
+    a.records = static_cast<int32_t*>(m->records.p);
+    a.rec_stride = stride;
+    a.rec_cap = shots;
+    a.keys = static_cast<unsigned long long*>(m->keys.p);
+    a.counters = cnt + (size_t)CNT_WORDS * i;
+  }
+  BucketArgs b;
+  memset(&b, 0, sizeof b);
+  b.shot_code = shot_code;
+  b.shots = shots;
+  b.n_codes = m->n;
+  b.lists = static_cast<int32_t*>(m->lists.p);
+  for (int i = 0; i < m->n; ++i) b.counts[i] = mixw + MIX_TASKS + i;
+  b.bad = mixw + MIX_BAD;
+  int grid[3];
+  for (int mode = 0; mode < 3; ++mode) {
+    int per_cu = 0;
+    if (mixed_dispatch(1, m->fam, fp64, uniform, mode, ma, lds, 0, nullptr, &per_cu) || per_cu < 1)
+      return fail(BPSF_EDEVICE, "occupancy query failed for mode %d", mode);
+    grid[mode] = per_cu * m->codes[0]->cus;
+  }
+  if (reset_counters(cnt, (int)words, stream)) return fail(BPSF_EDEVICE, "counter reset launch");
+  if (bucket_launch(b, stream)) return fail(BPSF_EDEVICE, "bucketing launch failed");
+  if (mixed_dispatch(0, m->fam, fp64, uniform, MODE_MAIN, ma, lds, grid[MODE_MAIN], stream, nullptr))
+    return fail(BPSF_EDEVICE, "first-BP launch failed");
+  if (p->k > 0) {
+    if (mixed_dispatch(0, m->fam, fp64, uniform, MODE_CAND, ma, lds, grid[MODE_CAND], stream, nullptr))
+      return fail(BPSF_EDEVICE, "trial launch failed");
+    if (mixed_dispatch(0, m->fam, fp64, uniform, MODE_EMIT, ma, lds, grid[MODE_EMIT], stream, nullptr))
+      return fail(BPSF_EDEVICE, "re-run launch failed");
+  }
+  return 0;
+}
+
+int bpsf_mix_last_stats(bpsf_mix m, void* stream, bpsf_stats* per_code, int64_t* invalid_shots)
+{
+  if (!m || !per_code) return fail(BPSF_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(m->mu);
+  for (int i = 0; i < m->n; ++i) memset(&per_code[i], 0, sizeof per_code[i]);
+  if (invalid_shots) *invalid_shots = 0;
+  if (!m->counters.p) return 0;
+  std::vector<unsigned long long> h((size_t)CNT_WORDS * m->n + MIX_WORDS);
+  HIP_OK(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  HIP_OK(hipMemcpy(h.data(), m->counters.p, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost));
+  for (int i = 0; i < m->n; ++i) {
+    const unsigned long long* w = h.data() + (size_t)CNT_WORDS * i;
+    per_code[i].main_iterations = (int64_t)w[ST_MAIN_ITERS];
+    per_code[i].trial_iterations = (int64_t)w[ST_CAND_ITERS];
+    per_code[i].rerun_iterations = (int64_t)w[ST_EMIT_ITERS];
+    per_code[i].failed_shots = (int64_t)w[CNT_FAILED];
+    per_code[i].converged_trials = (int64_t)w[ST_CAND_CONV];
+    per_code[i].errors = (int64_t)w[ST_ERRORS];
+  }
+  if (invalid_shots) *invalid_shots = (int64_t)h[(size_t)CNT_WORDS * m->n + MIX_BAD];
   return 0;
 }
 

@@ -654,9 +654,8 @@ __device__ __forceinline__ long long phase_tasks(const Args& a)
 // takes the codes after it in turn, so waves whose code runs out help the
 // others.
 template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE>
-__global__ __launch_bounds__(64) void bpsf_mixed_kernel(const MixArgs* __restrict__ mp)
+__global__ __launch_bounds__(64) void bpsf_mixed_kernel(const MixArgs m)
 {
-  const MixArgs& m = *mp;   // device copy written by the host before the launch
   float w[MIX_MAX_CODES];
   float total = 0.f;
   for (int c = 0; c < m.n_codes; ++c) {
@@ -733,7 +732,7 @@ static int run_mode(int what, int mode, bool trace, const Args& a, size_t lds, i
 }
 
 template <typename Real, int IC, int IV, int W, int DV, bool UL>
-static int run_mixed(int what, int mode, const MixArgs* m, size_t lds, int grid, hipStream_t st, int* out)
+static int run_mixed(int what, int mode, const MixArgs& m, size_t lds, int grid, hipStream_t st, int* out)
 {
   if (what == 1) {
     hipError_t e;
@@ -790,7 +789,7 @@ int tile_dispatch(int what, const TileDesc& t, bool fp64, bool ul, int mode, boo
   return -2;   // no such family compiled
 }
 
-int mixed_dispatch(int what, int fam, bool fp64, bool ul, int mode, const MixArgs* m, size_t lds, int grid,
+int mixed_dispatch(int what, int fam, bool fp64, bool ul, int mode, const MixArgs& m, size_t lds, int grid,
                    void* stream, int* out)
 {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);

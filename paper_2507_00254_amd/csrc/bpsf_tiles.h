@@ -90,8 +90,8 @@ FamilyDesc family_desc(int fam);
 // what = 0: launch; what = 1: *out = resident blocks per CU
 int tile_dispatch(int what, const TileDesc& t, bool fp64, bool uniform_llr, int mode, bool trace,
                   const Args& a, size_t lds_bytes, int grid, void* stream, int* out);
-// m: device copy of the launch's MixArgs (every code of one family)
-int mixed_dispatch(int what, int fam, bool fp64, bool uniform_llr, int mode, const MixArgs* m, size_t lds_bytes,
+// every code of m belongs to family fam
+int mixed_dispatch(int what, int fam, bool fp64, bool uniform_llr, int mode, const MixArgs& m, size_t lds_bytes,
                    int grid, void* stream, int* out);
 int bucket_launch(const BucketArgs& b, void* stream);
 int reset_counters(unsigned long long* c, int n, void* stream);   // zero n words

@@ -1,0 +1,134 @@
+"""Shots of several codes decoded in one call (bpsf_mix_*): every shot's result
+equals the single-code call's and the oracle's, per-code work counters add
+up to the single-code calls', and rows, padding and bad code indices are
+handled as the header states."""
+import numpy as np
+import pytest
+
+from tests import gpu_util as U
+from workloads import codes, shots
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ["bb72", "bb90", "bb108", "bb144", "bb288"]
+
+
+def _mix_decode(hs, shot_code, syn, priors, prm, precision="f32", corr_stride=None):
+    import torch
+    from paper_2507_00254_amd import bpsf as B
+    handles = [B.bpsf_load_code(h) for h in hs]
+    mix = B.bpsf_mix_create(handles)
+    try:
+        bp = B.make_params(prm.max_iter, prm.cand_max_iter, prm.k, prm.cand_mode, prm.w_max, prm.select_mode,
+                           prm.alpha, prm.flags, B.PREC_FP64 if precision == "f64" else B.PREC_FP32)
+        n = len(shot_code)
+        width = corr_stride or max(h.shape[1] for h in hs)
+        sc = torch.from_numpy(np.ascontiguousarray(shot_code, dtype=np.int32)).cuda()
+        s = torch.from_numpy(np.ascontiguousarray(syn, dtype=np.uint8)).cuda()
+        corr = torch.full((n, width), 7, dtype=torch.uint8, device="cuda")
+        conv = torch.full((n,), 7, dtype=torch.uint8, device="cuda")
+        it = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+        B.bpsf_mix_decode(mix, sc, s, priors, bp, corr, conv, it)
+        torch.cuda.synchronize()
+        st, bad = B.bpsf_mix_last_stats(mix, len(hs))
+        return {"correction": corr.cpu().numpy(), "converged": conv.cpu().numpy(),
+                "iterations": it.cpu().numpy(), "stats": st, "bad": bad}
+    finally:
+        B.bpsf_mix_free(mix)
+        for h in handles:
+            B.bpsf_free_code(h)
+
+
+def _per_code(out, shot_code, c, n_bits):
+    sel = np.nonzero(shot_code == c)[0]
+    return {"correction": out["correction"][sel, :n_bits], "converged": out["converged"][sel],
+            "iterations": out["iterations"][sel]}, sel
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_mixed_five_codes_match_single_calls_and_oracle(precision):
+    p, per = 0.05, 500
+    hs = [codes.get_code(n).hx for n in NAMES]
+    sc, syn, _, _ = shots.mixed_batch(hs, p, per, shots.stream_key(shots.MASTER_SEED, 900))
+    prm = U.oracle_params(k=6)
+    print(f"mixed {precision} {len(sc)} shots", flush=True)
+    out = _mix_decode(hs, sc, syn, [np.full(h.shape[1], p) for h in hs], prm, precision)
+    assert out["bad"] == 0
+    for c, h in enumerate(hs):
+        g, sel = _per_code(out, sc, c, h.shape[1])
+        s_c = syn[sel, :h.shape[0]]
+        one = U.gpu_decode(h, s_c, p, prm, precision=precision)
+        assert len(U.mismatches(g, one)) == 0, NAMES[c]
+        o = U.oracle_decode(h, s_c, p, prm, precision=precision)
+        assert len(U.mismatches(g, o)) == 0, NAMES[c]
+        # padding after the code's N bits is left alone
+        assert (out["correction"][sel, h.shape[1]:] == 7).all()
+        st = out["stats"][c]
+        for f in ("main_iterations", "trial_iterations", "rerun_iterations", "failed_shots", "converged_trials"):
+            assert st[f] == one["stats"][f], (NAMES[c], f)
+        assert st["errors"] == 0
+
+
+def test_mixed_missing_code_and_bad_indices():
+    p = 0.06
+    hs = [codes.get_code(n).hx for n in ("bb72", "bb144", "bb288")]
+    sc, syn, _, _ = shots.mixed_batch(hs, p, 300, shots.stream_key(shots.MASTER_SEED, 901))
+    sc = sc.copy()
+    sc[sc == 1] = 0                      # no bb144 shot at all
+    bad_at = np.array([3, 50, 777])
+    sc[bad_at] = [-1, 3, 1 << 20]        # out of range: skipped
+    prm = U.oracle_params(k=6)
+    out = _mix_decode(hs, sc, syn, [np.full(h.shape[1], p) for h in hs], prm)
+    assert out["bad"] == len(bad_at)
+    assert (out["correction"][bad_at] == 7).all() and (out["converged"][bad_at] == 7).all()
+    assert (out["iterations"][bad_at] == -1).all()
+    assert out["stats"][1]["main_iterations"] == 0 and out["stats"][1]["failed_shots"] == 0
+    for c in (0, 2):
+        h = hs[c]
+        g, sel = _per_code(out, sc, c, h.shape[1])
+        o = U.oracle_decode(h, syn[sel, :h.shape[0]], p, prm, precision="f32")
+        assert len(U.mismatches(g, o)) == 0
+
+
+def test_mixed_single_code_and_nonuniform_priors():
+    """One code in a mix, then two codes one of whose priors vary per bit (the
+    launch then takes the per-bit LLR path for both)."""
+    h72, h144 = codes.get_code("bb72").hx, codes.get_code("bb144").hx
+    rng = np.random.default_rng(3)
+    pri144 = rng.uniform(0.01, 0.08, h144.shape[1])
+    sc, syn, _, _ = shots.mixed_batch([h72, h144], 0.05, 400, shots.stream_key(shots.MASTER_SEED, 902))
+    prm = U.oracle_params(k=5)
+    out = _mix_decode([h72, h144], sc, syn, [np.full(72, 0.05), pri144], prm)
+    for c, (h, pri) in enumerate(((h72, 0.05), (h144, pri144))):
+        g, sel = _per_code(out, sc, c, h.shape[1])
+        o = U.oracle_decode(h, syn[sel, :h.shape[0]], pri, prm, precision="f32")
+        assert len(U.mismatches(g, o)) == 0
+    only = np.zeros(257, np.int32)
+    _, s1 = shots.make_shots(h144, 0.05, 257, shots.stream_key(shots.MASTER_SEED, 903))
+    out1 = _mix_decode([h144], only, s1, [np.full(144, 0.05)], prm)
+    o1 = U.oracle_decode(h144, s1, 0.05, prm, precision="f32")
+    assert len(U.mismatches(out1, o1)) == 0
+
+
+def test_mixed_rejects_bad_arguments():
+    import torch
+    from paper_2507_00254_amd import bpsf as B
+    h72 = codes.get_code("bb72").hx
+    a = B.bpsf_load_code(h72)
+    try:
+        with pytest.raises(B.BpsfError):
+            B.bpsf_mix_create([a, a])                       # repeated handle
+        mix = B.bpsf_mix_create([a])
+        try:
+            bp = B.make_params(100, 20, 4, 0, 1, 0, 0.625, 0, B.PREC_FP32)
+            sc = torch.zeros(4, dtype=torch.int32, device="cuda")
+            s = torch.zeros((4, 30), dtype=torch.uint8, device="cuda")      # stride < M = 36
+            corr = torch.zeros((4, 72), dtype=torch.uint8, device="cuda")
+            conv = torch.zeros(4, dtype=torch.uint8, device="cuda")
+            it = torch.zeros(4, dtype=torch.int32, device="cuda")
+            with pytest.raises(B.BpsfError):
+                B.bpsf_mix_decode(mix, sc, s, [np.full(72, 0.05)], bp, corr, conv, it)
+        finally:
+            B.bpsf_mix_free(mix)
+    finally:
+        B.bpsf_free_code(a)

@@ -80,3 +80,30 @@ def random_syndromes(m: int, n_shots: int, key: np.uint64, density: float = 0.5)
     """Arbitrary (not necessarily feasible-by-low-weight) syndromes, for edge cases."""
     u = uniforms(key, 0, n_shots * m).reshape(n_shots, m)
     return (u < density).astype(np.uint8)
+
+
+def interleave_order(key: np.uint64, n: int) -> np.ndarray:
+    """A seeded permutation of ``range(n)`` (shots sorted by a counter-based
+    hash of their position)."""
+    return np.argsort(_mix(np.uint64(key) ^ np.arange(n, dtype=np.uint64)), kind="stable")
+
+
+def mixed_batch(hs, p: float, per_code: int, key: np.uint64):
+    """Shots of several check matrices mixed in one batch: ``per_code`` seeded
+    shots of each ``hs[c]`` (stream ``stream_key(key, c)``) interleaved by a
+    seeded permutation. Returns ``(shot_code int32 [n], syndromes uint8
+    [n, max M] zero-padded, errors list per code, order)`` where ``order[i]``
+    is the position in the code-major concatenation of shot ``i``."""
+    n_codes = len(hs)
+    mmax = max(h.shape[0] for h in hs)
+    errs, syns = [], []
+    for c, h in enumerate(hs):
+        e, s = make_shots(h, p, per_code, stream_key(int(key), c))
+        errs.append(e)
+        pad = np.zeros((per_code, mmax), np.uint8)
+        pad[:, :h.shape[0]] = s
+        syns.append(pad)
+    code_major = np.concatenate(syns)
+    codes_major = np.repeat(np.arange(n_codes, dtype=np.int32), per_code)
+    order = interleave_order(stream_key(int(key), 0x6d6978), n_codes * per_code)
+    return codes_major[order], np.ascontiguousarray(code_major[order]), errs, order
