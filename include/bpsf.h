@@ -193,6 +193,30 @@ int bpsf_mix_decode(bpsf_mix mix, const int32_t* shot_code, const uint8_t* syndr
  * Waits for `stream`. */
 int bpsf_mix_last_stats(bpsf_mix mix, void* stream, bpsf_stats* per_code, int64_t* invalid_shots);
 
+/*
+ * Launch shape. A decode kernel runs D decodes per wavefront ("decodes per
+ * wave", a power of two; 64 / D lanes per decode) in a persistent grid of
+ * W waves per compute unit. Results do not depend on either.
+ * bpsf_tile_options writes the D values the code fits, most first, to host
+ * d_out (up to cap) and returns their number. bpsf_set_tile fixes D and W
+ * for later calls on the handle (0 = default: the largest D that fits, as
+ * many waves as fit). bpsf_autotune times bpsf_decode on a sample (device
+ * syndromes [shots][M], host priors, as for bpsf_decode; best of `reps`
+ * calls after one untimed call) for every D and a range of W, keeps the
+ * fastest on the handle and describes it in *out (host). It allocates and
+ * frees output buffers for the sample and synchronizes `stream`.
+ */
+typedef struct {
+  int32_t decodes_per_wave;  /* D chosen */
+  int32_t waves_per_cu;      /* W chosen */
+  float ms;                  /* its time on the sample */
+  int32_t candidates;        /* (D, W) pairs timed */
+} bpsf_tuning;
+int bpsf_tile_options(bpsf_code code, int32_t* d_out, int32_t cap);
+int bpsf_set_tile(bpsf_code code, int32_t decodes_per_wave, int32_t waves_per_cu);
+int bpsf_autotune(bpsf_code code, const uint8_t* syndromes, const double* priors, int64_t shots,
+                  const bpsf_params* params, int32_t reps, void* stream, bpsf_tuning* out);
+
 /* Shape of a loaded code: M, N, edges, row weight, column weight (host outs, any may be NULL). */
 int bpsf_code_info(bpsf_code code, int32_t* M, int32_t* N, int32_t* edges, int32_t* row_weight,
                    int32_t* col_weight);

@@ -34,6 +34,11 @@ class bpsf_stats(C.Structure):
                 ("converged_trials", C.c_int64), ("errors", C.c_int64)]
 
 
+class bpsf_tuning(C.Structure):
+    _fields_ = [("decodes_per_wave", C.c_int32), ("waves_per_cu", C.c_int32), ("ms", C.c_float),
+                ("candidates", C.c_int32)]
+
+
 class BpsfError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libbpsf error {code}: {msg}")
@@ -41,6 +46,9 @@ class BpsfError(RuntimeError):
 
 
 def _load():
+    # torch brings its own HIP runtime; it has to be in the process before
+    # this library resolves libamdhip64, or torch later finds no GPU
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2507_00254_amd/build.py "
                           "(or __graft_entry__.build())")
@@ -59,6 +67,9 @@ def _load():
     lib.bpsf_set_timing.argtypes = [vp, C.c_int]
     lib.bpsf_last_timing.argtypes = [vp, P(C.c_float)]
     lib.bpsf_code_info.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(i32)]
+    lib.bpsf_tile_options.argtypes = [vp, P(i32), i32]
+    lib.bpsf_set_tile.argtypes = [vp, i32, i32]
+    lib.bpsf_autotune.argtypes = [vp, vp, P(C.c_double), i64, P(bpsf_params), i32, vp, P(bpsf_tuning)]
     lib.bpsf_mix_create.argtypes = [P(vp), i32, P(vp)]
     lib.bpsf_mix_free.argtypes = [vp]
     lib.bpsf_mix_free.restype = None
@@ -155,6 +166,28 @@ def bpsf_last_timing(handle) -> dict:
     ms = (C.c_float * 4)()
     _check(LIB.bpsf_last_timing(C.c_void_p(handle), ms))
     return {"total": ms[0], "main": ms[1], "trials": ms[2], "rerun": ms[3]}
+
+
+def bpsf_tile_options(handle) -> list:
+    """Decodes per wave the code fits, most first."""
+    buf = (C.c_int32 * 8)()
+    n = LIB.bpsf_tile_options(C.c_void_p(handle), buf, 8)
+    _check(n if n < 0 else 0)
+    return [buf[i] for i in range(min(n, 8))]
+
+
+def bpsf_set_tile(handle, decodes_per_wave: int = 0, waves_per_cu: int = 0) -> None:
+    _check(LIB.bpsf_set_tile(C.c_void_p(handle), int(decodes_per_wave), int(waves_per_cu)))
+
+
+def bpsf_autotune(handle, syndromes, priors, params: bpsf_params, reps: int = 3, stream=None) -> dict:
+    """Time every launch shape on a device sample of syndromes; keep the fastest."""
+    pri = np.ascontiguousarray(priors, dtype=np.float64)
+    out = bpsf_tuning()
+    _check(LIB.bpsf_autotune(C.c_void_p(handle), C.c_void_p(syndromes.data_ptr()),
+                             pri.ctypes.data_as(C.POINTER(C.c_double)), int(syndromes.shape[0]), C.byref(params),
+                             int(reps), _stream_ptr(stream), C.byref(out)))
+    return {f: getattr(out, f) for f, _ in bpsf_tuning._fields_}
 
 
 def bpsf_mix_create(handles) -> int:

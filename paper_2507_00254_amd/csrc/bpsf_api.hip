@@ -74,7 +74,8 @@ struct bpsf_code_s {
   DevBuf masks;
   // scratch
   DevBuf records, keys, counters;
-  int tuned_D = 0;            // decodes per wave chosen by bpsf_autotune (0: default)
+  int tuned_D = 0;            // decodes per wave (0: the most that fit)
+  int tuned_wpc = 0;          // resident waves per CU of the persistent grids (0: as many as fit)
   // optional per-phase timing: events[i] marks the boundary before phase i
   bool timing = false;
   bool timed_last = false;
@@ -276,6 +277,7 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
     int per_cu = 0;
     if (tile_dispatch(1, t, fp64, c->uniform, mode, false, a, pl->lds, 0, nullptr, &per_cu) || per_cu < 1)
       return fail(BPSF_EDEVICE, "occupancy query failed for mode %d", mode);
+    if (c->tuned_wpc > 0 && c->tuned_wpc < per_cu) per_cu = c->tuned_wpc;
     pl->grid[mode] = per_cu * c->cus;
   }
   return 0;
@@ -680,6 +682,109 @@ int bpsf_mix_last_stats(bpsf_mix m, void* stream, bpsf_stats* per_code, int64_t*
     per_code[i].errors = (int64_t)w[ST_ERRORS];
   }
   if (invalid_shots) *invalid_shots = (int64_t)h[(size_t)CNT_WORDS * m->n + MIX_BAD];
+  return 0;
+}
+
+int bpsf_tile_options(bpsf_code c, int32_t* d_out, int32_t cap)
+{
+  if (!c) return fail(BPSF_EINVAL, "code is NULL");
+  int n = 0;
+  for (int fam = 0; fam < family_count(); ++fam)
+    for (int D = MAX_D; D >= 1; D >>= 1)
+      if (tile_fits(c, fam, D)) {
+        if (d_out && n < cap) d_out[n] = D;
+        ++n;
+      }
+  return n;
+}
+
+int bpsf_set_tile(bpsf_code c, int32_t decodes_per_wave, int32_t waves_per_cu)
+{
+  if (!c) return fail(BPSF_EINVAL, "code is NULL");
+  if (waves_per_cu < 0) return fail(BPSF_EINVAL, "waves_per_cu < 0");
+  bool ok = decodes_per_wave == 0;
+  for (int fam = 0; fam < family_count() && !ok; ++fam) ok = tile_fits(c, fam, decodes_per_wave);
+  if (!ok) return fail(BPSF_EINVAL, "the code does not fit %d decodes per wave", decodes_per_wave);
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->tuned_D = decodes_per_wave;
+  c->tuned_wpc = waves_per_cu;
+  return 0;
+}
+
+int bpsf_autotune(bpsf_code c, const uint8_t* syndromes, const double* priors, int64_t shots,
+                  const bpsf_params* p, int32_t reps, void* stream, bpsf_tuning* out)
+{
+  if (!c || !out) return fail(BPSF_EINVAL, "NULL argument");
+  if (shots < 1 || !syndromes) return fail(BPSF_EINVAL, "need a sample of at least one shot");
+  if (reps < 1) return fail(BPSF_EINVAL, "reps < 1");
+  int rc = check_params(p);
+  if (rc) return rc;
+  memset(out, 0, sizeof *out);
+  DevBuf corr, conv, it;
+  if (corr.ensure((size_t)shots * c->N) || conv.ensure((size_t)shots) || it.ensure(sizeof(int32_t) * (size_t)shots))
+    return fail(BPSF_ENOMEM, "autotune outputs");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  int32_t ds[8];
+  const int nd = bpsf_tile_options(c, ds, 8);
+  const int saved_D = c->tuned_D, saved_w = c->tuned_wpc;
+  float best = 0.f;
+  int best_D = 0, best_w = 0, tried = 0;
+  rc = 0;
+  for (int i = 0; i < nd && !rc; ++i) {
+    // resident waves per CU this tile allows
+    int max_w = 0;
+    {
+      std::lock_guard<std::mutex> lk(c->mu);
+      c->tuned_D = ds[i];
+      c->tuned_wpc = 0;
+      if ((rc = update_llr(c, priors)) || (rc = update_masks(c, p))) break;
+      Plan pl;
+      if ((rc = make_plan(c, p, shots, &pl))) break;
+      max_w = pl.grid[MODE_MAIN] / c->cus;
+    }
+    for (int w = max_w; w >= 1 && !rc; w = w > 2 ? w - 2 : w - 1) {
+      {
+        std::lock_guard<std::mutex> lk(c->mu);
+        c->tuned_D = ds[i];
+        c->tuned_wpc = w;
+      }
+      // one untimed call, then the best of `reps`
+      float t_best = 0.f;
+      for (int r = 0; r <= reps && !rc; ++r) {
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(BPSF_EDEVICE, "event record"); break; }
+        rc = bpsf_decode(c, syndromes, priors, shots, p, static_cast<uint8_t*>(corr.p), static_cast<uint8_t*>(conv.p),
+                         static_cast<int32_t*>(it.p), stream);
+        if (rc) break;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          rc = fail(BPSF_EDEVICE, "event wait");
+          break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (r > 0 && (t_best == 0.f || ms < t_best)) t_best = ms;
+      }
+      if (rc) break;
+      ++tried;
+      if (best == 0.f || t_best < best) { best = t_best; best_D = ds[i]; best_w = w; }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (rc) {
+    c->tuned_D = saved_D;
+    c->tuned_wpc = saved_w;
+    return rc;
+  }
+  c->tuned_D = best_D;
+  c->tuned_wpc = best_w;
+  out->decodes_per_wave = best_D;
+  out->waves_per_cu = best_w;
+  out->ms = best;
+  out->candidates = tried;
   return 0;
 }
 

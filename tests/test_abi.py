@@ -42,6 +42,7 @@ def test_params_layout(B):
     assert C.sizeof(B.bpsf_params) == 40
     assert B.bpsf_params.alpha.offset == 24
     assert C.sizeof(B.bpsf_stats) == 48
+    assert C.sizeof(B.bpsf_tuning) == 16
 
 
 def test_trial_enumeration_matches_oracle(B):

@@ -1,0 +1,53 @@
+"""Launch shapes: every decodes-per-wave and grid size gives bit-identical
+results and work counts, and the autotuner picks one of them."""
+import numpy as np
+import pytest
+
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name,p", [("bb72", 0.06), ("bb144", 0.05), ("bb288", 0.04)])
+def test_every_tile_gives_the_same_results(name, p):
+    from paper_2507_00254_amd import bpsf as B
+    code, _, syn = U.inputs(name, p, 1500, tag=20)
+    prm = U.oracle_params(k=6)
+    h = B.bpsf_load_code(code.hx)
+    try:
+        opts = B.bpsf_tile_options(h)
+        assert opts and opts == sorted(opts, reverse=True) and all(64 % d == 0 for d in opts)
+        ref = U.gpu_decode(code.hx, syn, p, prm, handle=h)
+        o = U.oracle_decode(code.hx, syn, p, prm, precision="f32")
+        assert len(U.mismatches(ref, o)) == 0
+        for d in opts:
+            for w in (0, 1, 3):
+                print(f"{name} D={d} W={w}", flush=True)
+                B.bpsf_set_tile(h, d, w)
+                g = U.gpu_decode(code.hx, syn, p, prm, handle=h)
+                assert len(U.mismatches(g, ref)) == 0, (d, w)
+                assert g["stats"] == ref["stats"], (d, w)
+        with pytest.raises(B.BpsfError):
+            B.bpsf_set_tile(h, 32, 0)        # 2 lanes per decode: no family fits
+    finally:
+        B.bpsf_free_code(h)
+
+
+def test_autotune_picks_a_listed_tile_and_keeps_results():
+    import torch
+    from paper_2507_00254_amd import bpsf as B
+    code, _, syn = U.inputs("bb144", 0.03, 20000, tag=21)
+    prm = U.oracle_params(k=6)
+    h = B.bpsf_load_code(code.hx)
+    try:
+        bp = B.make_params(prm.max_iter, prm.cand_max_iter, prm.k, alpha=prm.alpha, precision=B.PREC_FP32)
+        s = torch.from_numpy(syn).cuda()
+        t = B.bpsf_autotune(h, s, np.full(code.n, 0.03), bp, reps=2)
+        print(t, flush=True)
+        assert t["decodes_per_wave"] in B.bpsf_tile_options(h)
+        assert t["waves_per_cu"] >= 1 and t["ms"] > 0 and t["candidates"] >= len(B.bpsf_tile_options(h))
+        g = U.gpu_decode(code.hx, syn[:3000], 0.03, prm, handle=h)
+        o = U.oracle_decode(code.hx, syn[:3000], 0.03, prm, precision="f32")
+        assert len(U.mismatches(g, o)) == 0
+    finally:
+        B.bpsf_free_code(h)
