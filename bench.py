@@ -206,6 +206,64 @@ def run_mixed(args):
     print(json.dumps(out), flush=True)
 
 
+def run_serve(args):
+    """Open-loop serving of the five-code mix: Poisson arrivals of requests of
+    U{1..256} shots of a uniformly drawn code, at each offered load, through
+    the batched server and through the per-request server on the same
+    requests. Latency = completion - scheduled arrival."""
+    import torch
+
+    from paper_2507_00254_amd import bpsf as B
+    from workloads import codes, shots
+
+    torch.cuda.set_device(0)
+    p = args.p
+    hs = [codes.get_code(nm).hx for nm in MIXED_NAMES]
+    pools = [shots.make_shots(h, p, 60000, shots.stream_key(shots.MASTER_SEED, 5, c))[1] for c, h in enumerate(hs)]
+    handles = [B.bpsf_load_code(h) for h in hs]
+    prm = B.make_params(max_iter=100, cand_max_iter=20, k=6, alpha=0.625, precision=B.PREC_FP32)
+    pri = [np.full(h.shape[1], p) for h in hs]
+    points = []
+    for li, load in enumerate(float(x) for x in args.loads.split(",")):
+        rng = np.random.default_rng(1000 + li)
+        n_req = int(min(max(3000, args.min_requests), max(args.min_requests, load * 0.4 / 128.5)))
+        code = rng.integers(0, len(hs), n_req).astype(np.int32)
+        size = rng.integers(1, 257, n_req)
+        gaps = rng.exponential(128.5 / load, n_req)
+        arrival = np.cumsum(gaps) - gaps[0]
+        offs = rng.integers(0, 60000 - 256, n_req)
+        syns = [pools[c][o:o + n] for c, o, n in zip(code, offs, size)]
+        total = int(size.sum())
+        row = {"offered_shots_per_s": load, "requests": n_req, "shots": total}
+        outs = {}
+        for mode, batching, lanes in (("batched", True, args.lanes), ("per_request", False, 1)):
+            srv = B.Server(handles, pri, prm, lanes=lanes, max_batch_shots=65536, batching=batching)
+            try:
+                srv.replay(arrival[:20], code[:20], syns[:20])          # warm: tables, scratch, streams
+                lat, wall, out = srv.replay(arrival, code, syns)
+                cnt = srv.counters()
+            finally:
+                srv.close()
+            outs[mode] = out
+            row[mode] = {"shots_per_s": total / wall, "wall_s": wall,
+                         "p50_us": float(np.percentile(lat, 50) * 1e6), "p99_us": float(np.percentile(lat, 99) * 1e6),
+                         "max_us": float(lat.max() * 1e6), "batches": cnt["batches"] - (20 if not batching else 0)}
+        diff = sum(int((a[0] != b[0]).any(axis=1).sum() + (a[1] != b[1]).sum())
+                   for a, b in zip(outs["batched"], outs["per_request"]))
+        row["shots_differing_between_modes"] = diff
+        row["converged_rate"] = float(np.mean(np.concatenate([o[1] for o in outs["batched"]])))
+        print(json.dumps(row), flush=True)
+        points.append(row)
+    for h in handles:
+        B.bpsf_free_code(h)
+    out = {"metric": "open-loop serving of the five-code mix: throughput and latency vs offered load",
+           "unit": "shots/s", "n_gpus": 1, "dtype": "f32", "lanes": args.lanes,
+           "data": "synthetic (seeded i.i.d. bit flips p=%g, Poisson arrivals, request sizes U{1..256})" % p,
+           "config": {"workload": "serve_mixed5", "codes": list(MIXED_NAMES), "max_batch_shots": 65536},
+           "points": points}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,8 +274,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-calls", type=int, default=200)
-    ap.add_argument("--workload", choices=("bb144", "mixed5"), default="bb144",
-                    help="bb144: the headline workload; mixed5: five BB codes' shots interleaved in one call")
+    ap.add_argument("--workload", choices=("bb144", "mixed5", "serve"), default="bb144",
+                    help="bb144: the headline workload; mixed5: five BB codes' shots interleaved in one call; "
+                         "serve: open-loop request serving, batched vs per-request, over a load sweep")
+    ap.add_argument("--loads", type=str, default="1e4,3e4,1e5,3e5,1e6,3e6,1e7",
+                    help="serve: offered loads in shots/s")
+    ap.add_argument("--lanes", type=int, default=2, help="serve: streams of the batched server")
+    ap.add_argument("--min-requests", type=int, default=400, help="serve: requests per load point at least")
     ap.add_argument("--per-code", type=int, default=200_000, help="mixed5: shots of each code")
     ap.add_argument("--copy-calibration", action="store_true", help="run only the plain copy used to scale counters")
     ap.add_argument("--traffic-summary", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
@@ -236,6 +299,9 @@ def main():
         sys.exit(2)
     if args.workload == "mixed5":
         run_mixed(args)
+        return
+    if args.workload == "serve":
+        run_serve(args)
         return
 
     import torch

@@ -116,6 +116,14 @@ int bpsf_decode(bpsf_code code, const uint8_t* syndromes, const double* priors, 
                 const bpsf_params* params, uint8_t* corrections, uint8_t* converged, int32_t* iterations,
                 void* stream);
 
+/*
+ * Grow the handle's scratch now for calls of up to `shots` shots with these
+ * parameters (their k and the code's launch shape set the record size), so
+ * that such calls allocate nothing: for callers that cannot allocate later,
+ * e.g. under HIP graph capture or in a serving loop. Synchronous.
+ */
+int bpsf_reserve(bpsf_code code, int64_t shots, const bpsf_params* params);
+
 /* Work counters of the last bpsf_decode on `code` (host out). Waits for `stream`. */
 int bpsf_last_stats(bpsf_code code, void* stream, bpsf_stats* out);
 
@@ -188,6 +196,19 @@ int bpsf_mix_decode(bpsf_mix mix, const int32_t* shot_code, const uint8_t* syndr
                     uint8_t* corrections, int64_t corr_stride, uint8_t* converged, int32_t* iterations,
                     void* stream);
 
+/* bpsf_reserve for a mix: its scratch for calls of up to `shots` shots. */
+int bpsf_mix_reserve(bpsf_mix mix, int64_t shots, const bpsf_params* params);
+
+/*
+ * As bpsf_mix_decode, with the shots grouped by code instead of listed:
+ * counts (host int64 [n_codes]) gives each code's number of shots, and code
+ * c's shots are the counts[c] rows following those of codes 0..c-1 (no
+ * device-side grouping pass; shots = the sum of counts).
+ */
+int bpsf_mix_decode_grouped(bpsf_mix mix, const int64_t* counts, const uint8_t* syndromes, int64_t syn_stride,
+                            const double* const* priors, const bpsf_params* params, uint8_t* corrections,
+                            int64_t corr_stride, uint8_t* converged, int32_t* iterations, void* stream);
+
 /* Work counters of the last bpsf_mix_decode, per code (host out [n_codes]),
  * and the number of shots whose code index was out of range (may be NULL).
  * Waits for `stream`. */
@@ -216,6 +237,53 @@ int bpsf_tile_options(bpsf_code code, int32_t* d_out, int32_t cap);
 int bpsf_set_tile(bpsf_code code, int32_t decodes_per_wave, int32_t waves_per_cu);
 int bpsf_autotune(bpsf_code code, const uint8_t* syndromes, const double* priors, int64_t shots,
                   const bpsf_params* params, int32_t reps, void* stream, bpsf_tuning* out);
+
+/*
+ * Request loop. A server decodes requests (a batch of 1..max_batch_shots host
+ * syndromes of one of its codes) as they arrive, on a worker thread of its
+ * own. Codes (up to 8, one kernel family when batching), their priors
+ * (host double [N] each, copied) and the parameters are fixed at creation.
+ *   batching = 1: continuous batching over `lanes` (1..8) streams. Whenever a
+ *     lane is free, every waiting request that fits in max_batch_shots is
+ *     admitted into one batch: copied to the device grouped by code,
+ *     decoded by one bpsf_mix_decode_grouped, copied back. Requests that arrive while batches run
+ *     wait for the next free lane, so batches overlap on the device. Device
+ *     memory per lane: max_batch_shots * (max M + max N + 5) bytes plus
+ *     its mix scratch; pinned host memory per lane: the same staging.
+ *   batching = 0: each request decoded alone with bpsf_decode on its code,
+ *     in arrival order, one at a time (lanes must be 1): the per-request form.
+ * Results are what bpsf_decode returns for each shot alone.
+ * bpsf_server_submit enqueues a request (host syndromes uint8 [n][M of the
+ * code]; outputs host corrections uint8 [n][N], converged uint8 [n],
+ * iterations int32 [n]; all must stay valid until the request is collected)
+ * and writes its id. bpsf_server_wait blocks until request `id` is done,
+ * collects it (the id is then unknown) and writes its latency from submission
+ * in seconds (may be NULL). bpsf_server_poll writes up to cap ids of requests
+ * completed since the last poll (host int64 out) and returns their number.
+ * bpsf_server_replay is an open-loop load driver on the calling thread:
+ * request i (code[i], shots[i], host buffers as for submit) is submitted
+ * arrival_s[i] seconds after the start (non-decreasing), whatever is still in
+ * flight; once all are done it collects them and writes latency_s[i] =
+ * completion - scheduled arrival and *wall_s (may be NULL) = the time from
+ * the start to the last completion. bpsf_server_counters reports batches
+ * launched, shots they held and requests completed. bpsf_server_destroy
+ * finishes the queued work and frees the server; it returns the first error
+ * the worker met, if any.
+ */
+typedef struct bpsf_server_s* bpsf_server;
+int bpsf_server_create(const bpsf_code* codes, int32_t n_codes, const double* const* priors,
+                       const bpsf_params* params, int32_t lanes, int64_t max_batch_shots, int32_t batching,
+                       bpsf_server* out);
+int bpsf_server_submit(bpsf_server server, int32_t code, const uint8_t* syndromes, int32_t n,
+                       uint8_t* corrections, uint8_t* converged, int32_t* iterations, int64_t* id_out);
+int bpsf_server_wait(bpsf_server server, int64_t id, double* latency_s_out);
+int64_t bpsf_server_poll(bpsf_server server, int64_t* ids_out, int64_t cap);
+int bpsf_server_replay(bpsf_server server, int64_t n_requests, const double* arrival_s, const int32_t* code,
+                       const int32_t* shots, const uint8_t* const* syndromes, uint8_t* const* corrections,
+                       uint8_t* const* converged, int32_t* const* iterations, double* latency_s,
+                       double* wall_s);
+int bpsf_server_counters(bpsf_server server, int64_t* batches, int64_t* batch_shots, int64_t* requests_done);
+int bpsf_server_destroy(bpsf_server server);
 
 /* Shape of a loaded code: M, N, edges, row weight, column weight (host outs, any may be NULL). */
 int bpsf_code_info(bpsf_code code, int32_t* M, int32_t* N, int32_t* edges, int32_t* row_weight,

@@ -68,13 +68,26 @@ def _load():
     lib.bpsf_last_timing.argtypes = [vp, P(C.c_float)]
     lib.bpsf_code_info.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(i32)]
     lib.bpsf_tile_options.argtypes = [vp, P(i32), i32]
+    lib.bpsf_reserve.argtypes = [vp, i64, P(bpsf_params)]
+    lib.bpsf_mix_reserve.argtypes = [vp, i64, P(bpsf_params)]
     lib.bpsf_set_tile.argtypes = [vp, i32, i32]
     lib.bpsf_autotune.argtypes = [vp, vp, P(C.c_double), i64, P(bpsf_params), i32, vp, P(bpsf_tuning)]
     lib.bpsf_mix_create.argtypes = [P(vp), i32, P(vp)]
+    lib.bpsf_server_create.argtypes = [P(vp), i32, P(P(C.c_double)), P(bpsf_params), i32, i64, i32, P(vp)]
+    lib.bpsf_server_submit.argtypes = [vp, i32, vp, i32, vp, vp, vp, P(i64)]
+    lib.bpsf_server_wait.argtypes = [vp, i64, P(C.c_double)]
+    lib.bpsf_server_poll.argtypes = [vp, P(i64), i64]
+    lib.bpsf_server_poll.restype = i64
+    lib.bpsf_server_replay.argtypes = [vp, i64, P(C.c_double), P(i32), P(i32), P(vp), P(vp), P(vp), P(vp),
+                                       P(C.c_double), P(C.c_double)]
+    lib.bpsf_server_counters.argtypes = [vp, P(i64), P(i64), P(i64)]
+    lib.bpsf_server_destroy.argtypes = [vp]
     lib.bpsf_mix_free.argtypes = [vp]
     lib.bpsf_mix_free.restype = None
     lib.bpsf_mix_decode.argtypes = [vp, vp, vp, i64, P(P(C.c_double)), i64, P(bpsf_params), vp, i64, vp, vp, vp]
     lib.bpsf_mix_last_stats.argtypes = [vp, vp, P(bpsf_stats), P(i64)]
+    lib.bpsf_mix_decode_grouped.argtypes = [vp, P(i64), vp, i64, P(P(C.c_double)), P(bpsf_params), vp, i64, vp, vp,
+                                            vp]
     lib.bpsf_last_error.argtypes = []
     lib.bpsf_last_error.restype = C.c_char_p
     return lib
@@ -168,6 +181,14 @@ def bpsf_last_timing(handle) -> dict:
     return {"total": ms[0], "main": ms[1], "trials": ms[2], "rerun": ms[3]}
 
 
+def bpsf_reserve(handle, shots: int, params: bpsf_params) -> None:
+    _check(LIB.bpsf_reserve(C.c_void_p(handle), int(shots), C.byref(params)))
+
+
+def bpsf_mix_reserve(mix, shots: int, params: bpsf_params) -> None:
+    _check(LIB.bpsf_mix_reserve(C.c_void_p(mix), int(shots), C.byref(params)))
+
+
 def bpsf_tile_options(handle) -> list:
     """Decodes per wave the code fits, most first."""
     buf = (C.c_int32 * 8)()
@@ -222,6 +243,23 @@ def bpsf_mix_decode(mix, shot_code, syndromes, priors, params: bpsf_params, corr
                                _stream_ptr(stream)))
 
 
+def bpsf_mix_decode_grouped(mix, counts, syndromes, priors, params: bpsf_params, corrections, converged, iterations,
+                            stream=None) -> None:
+    """As bpsf_mix_decode with code c's shots the counts[c] rows after those
+    of the codes before it."""
+    cnt = np.ascontiguousarray(counts, dtype=np.int64)
+    for t in (syndromes, corrections, converged, iterations):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("device tensors must be contiguous CUDA (HIP) tensors")
+    pri = [np.ascontiguousarray(x, dtype=np.float64) for x in priors]
+    parr = (C.POINTER(C.c_double) * len(pri))(*[x.ctypes.data_as(C.POINTER(C.c_double)) for x in pri])
+    _check(LIB.bpsf_mix_decode_grouped(C.c_void_p(mix), cnt.ctypes.data_as(C.POINTER(C.c_int64)),
+                                       C.c_void_p(syndromes.data_ptr()), int(syndromes.shape[1]), parr,
+                                       C.byref(params), C.c_void_p(corrections.data_ptr()), int(corrections.shape[1]),
+                                       C.c_void_p(converged.data_ptr()), C.c_void_p(iterations.data_ptr()),
+                                       _stream_ptr(stream)))
+
+
 def bpsf_mix_last_stats(mix, n_codes: int, stream=None):
     """Per-code work counters of the last mixed decode and the number of
     shots skipped for an out-of-range code index."""
@@ -229,6 +267,95 @@ def bpsf_mix_last_stats(mix, n_codes: int, stream=None):
     bad = C.c_int64()
     _check(LIB.bpsf_mix_last_stats(C.c_void_p(mix), _stream_ptr(stream), st, C.byref(bad)))
     return [{f: getattr(x, f) for f, _ in bpsf_stats._fields_} for x in st], bad.value
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data)
+
+
+class Server:
+    """A request loop over loaded codes (see bpsf_server_create). Request
+    buffers are numpy arrays; they are kept alive until collected."""
+
+    def __init__(self, handles, priors, params: bpsf_params, lanes: int = 2, max_batch_shots: int = 65536,
+                 batching: bool = True):
+        self._pri = [np.ascontiguousarray(x, dtype=np.float64) for x in priors]
+        parr = (C.POINTER(C.c_double) * len(self._pri))(*[x.ctypes.data_as(C.POINTER(C.c_double))
+                                                          for x in self._pri])
+        arr = (C.c_void_p * len(handles))(*handles)
+        out = C.c_void_p()
+        _check(LIB.bpsf_server_create(arr, len(handles), parr, C.byref(params), int(lanes), int(max_batch_shots),
+                                      int(bool(batching)), C.byref(out)))
+        self.h = out.value
+        self._live = {}
+
+    def submit(self, code: int, syndromes: np.ndarray):
+        """Enqueue host syndromes uint8 [n, M]; returns (id, corrections,
+        converged, iterations) whose arrays fill in once the request is done."""
+        syn = np.ascontiguousarray(syndromes, dtype=np.uint8)
+        n = syn.shape[0]
+        nbits = self._n_of(code)
+        corr = np.empty((n, nbits), np.uint8)
+        conv = np.empty(n, np.uint8)
+        it = np.empty(n, np.int32)
+        rid = C.c_int64()
+        _check(LIB.bpsf_server_submit(C.c_void_p(self.h), int(code), _ptr(syn), n, _ptr(corr), _ptr(conv), _ptr(it),
+                                      C.byref(rid)))
+        self._live[rid.value] = (syn, corr, conv, it)
+        return rid.value, corr, conv, it
+
+    def wait(self, rid: int) -> float:
+        lat = C.c_double()
+        try:
+            _check(LIB.bpsf_server_wait(C.c_void_p(self.h), int(rid), C.byref(lat)))
+        finally:
+            self._live.pop(rid, None)
+        return lat.value
+
+    def poll(self, cap: int = 4096):
+        ids = np.zeros(cap, np.int64)
+        n = LIB.bpsf_server_poll(C.c_void_p(self.h), ids.ctypes.data_as(C.POINTER(C.c_int64)), cap)
+        _check(n if n < 0 else 0)
+        return ids[:n].tolist()
+
+    def replay(self, arrival_s, codes, syndromes):
+        """Open-loop replay: request i (host syndromes[i] of codes[i]) submitted
+        arrival_s[i] s after the start. Returns (latencies_s, wall_s, outputs)."""
+        n = len(codes)
+        arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        cd = np.ascontiguousarray(codes, dtype=np.int32)
+        syns = [np.ascontiguousarray(x, dtype=np.uint8) for x in syndromes]
+        sh = np.array([x.shape[0] for x in syns], np.int32)
+        outs = [(np.empty((x.shape[0], self._n_of(int(c))), np.uint8), np.empty(x.shape[0], np.uint8),
+                 np.empty(x.shape[0], np.int32)) for x, c in zip(syns, cd)]
+        vp = C.c_void_p
+        psyn = (vp * n)(*[x.ctypes.data for x in syns])
+        pcor = (vp * n)(*[o[0].ctypes.data for o in outs])
+        pcon = (vp * n)(*[o[1].ctypes.data for o in outs])
+        pit = (vp * n)(*[o[2].ctypes.data for o in outs])
+        lat = np.zeros(n, np.float64)
+        wall = C.c_double()
+        dp = C.POINTER(C.c_double)
+        _check(LIB.bpsf_server_replay(C.c_void_p(self.h), n, arr.ctypes.data_as(dp),
+                                      cd.ctypes.data_as(C.POINTER(C.c_int32)), sh.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      psyn, pcor, pcon, pit, lat.ctypes.data_as(dp), C.byref(wall)))
+        return lat, wall.value, outs
+
+    def counters(self) -> dict:
+        v = [C.c_int64() for _ in range(3)]
+        _check(LIB.bpsf_server_counters(C.c_void_p(self.h), *[C.byref(x) for x in v]))
+        return dict(zip(("batches", "batch_shots", "requests_done"), (x.value for x in v)))
+
+    def close(self):
+        if self.h:
+            rc = LIB.bpsf_server_destroy(C.c_void_p(self.h))
+            self.h = None
+            self._live.clear()
+            _check(rc)
+
+    def _n_of(self, code: int) -> int:
+        # an out-of-range code is left for the library to reject
+        return len(self._pri[code]) if 0 <= code < len(self._pri) else 1
 
 
 def bpsf_code_info(handle) -> dict:

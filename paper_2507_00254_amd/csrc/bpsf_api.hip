@@ -9,9 +9,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/bpsf.h"
@@ -34,6 +36,16 @@ int fail(int code, const char* fmt, ...)
   g_err = buf;
   return code;
 }
+
+}  // namespace
+
+int bpsf::report_error(int code, const char* msg)
+{
+  g_err = msg;
+  return code;
+}
+
+namespace {
 
 #define HIP_OK(expr)                                                                  \
   do {                                                                                \
@@ -213,6 +225,35 @@ int update_masks(bpsf_code_s* c, const bpsf_params* p)
   return 0;
 }
 
+// Resident blocks per CU of a kernel at an LDS size (memoized: the answer
+// depends only on the kernel, the LDS bytes and the device).
+int occupancy(bool mixed, const TileDesc& t, bool fp64, bool uniform, int mode, size_t lds, const Args* a,
+              const MixArgs* m, int* out)
+{
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, int, int, int, size_t, int>, int> memo;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const auto key = std::make_tuple(dev, (int)mixed, t.fam, mixed ? 0 : t.D, (int)fp64 * 2 + (int)uniform, mode, lds,
+                                   0);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = memo.find(key);
+    if (it != memo.end()) {
+      *out = it->second;
+      return 0;
+    }
+  }
+  int n = 0;
+  const int rc = mixed ? mixed_dispatch(1, t.fam, fp64, uniform, mode, *m, lds, 0, nullptr, &n)
+                       : tile_dispatch(1, t, fp64, uniform, mode, false, *a, lds, 0, nullptr, &n);
+  if (rc || n < 1) return -1;
+  std::lock_guard<std::mutex> lk(mu);
+  memo[key] = n;
+  *out = n;
+  return 0;
+}
+
 struct Plan {
   TileDesc tile;
   Args args;
@@ -275,7 +316,7 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
   pl->lds = tile_lds(c, t, fp64, c->uniform);
   for (int mode = 0; mode < 3; ++mode) {
     int per_cu = 0;
-    if (tile_dispatch(1, t, fp64, c->uniform, mode, false, a, pl->lds, 0, nullptr, &per_cu) || per_cu < 1)
+    if (occupancy(false, t, fp64, c->uniform, mode, pl->lds, &a, nullptr, &per_cu))
       return fail(BPSF_EDEVICE, "occupancy query failed for mode %d", mode);
     if (c->tuned_wpc > 0 && c->tuned_wpc < per_cu) per_cu = c->tuned_wpc;
     pl->grid[mode] = per_cu * c->cus;
@@ -367,7 +408,9 @@ int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, in
   if (!rc && hipGetDeviceProperties(&prop, c->device) != hipSuccess) rc = fail(BPSF_EDEVICE, "hipGetDeviceProperties");
   if (!rc) {
     c->cus = prop.multiProcessorCount;
-    if (c->var_chk.ensure(vchk.size() * 2) || c->var_pos.ensure(vpos.size()) || c->ell_col.ensure(ell.size() * 4))
+    // var_chk padded to whole 32-bit words: the kernels copy it by words
+    if (c->var_chk.ensure((vchk.size() * 2 + 3) & ~(size_t)3) || c->var_pos.ensure(vpos.size()) ||
+        c->ell_col.ensure(ell.size() * 4))
       rc = fail(BPSF_ENOMEM, "code tables");
   }
   if (!rc && (hipMemcpy(c->var_chk.p, vchk.data(), vchk.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
@@ -563,9 +606,15 @@ void bpsf_mix_free(bpsf_mix m)
   delete m;
 }
 
-int bpsf_mix_decode(bpsf_mix m, const int32_t* shot_code, const uint8_t* syndromes, int64_t syn_stride,
-                    const double* const* priors, int64_t shots, const bpsf_params* p, uint8_t* corrections,
-                    int64_t corr_stride, uint8_t* converged, int32_t* iterations, void* stream)
+}  // extern "C"
+
+namespace {
+
+// Shots of the mix either listed by code index (shot_code, device) or
+// grouped: code c's shots are the counts[c] rows after those of codes < c.
+int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, const uint8_t* syndromes,
+               int64_t syn_stride, const double* const* priors, int64_t shots, const bpsf_params* p,
+               uint8_t* corrections, int64_t corr_stride, uint8_t* converged, int32_t* iterations, void* stream)
 {
   if (!m) return fail(BPSF_EINVAL, "mix is NULL");
   int rc = check_params(p);
@@ -577,7 +626,7 @@ int bpsf_mix_decode(bpsf_mix m, const int32_t* shot_code, const uint8_t* syndrom
     if (syn_stride < m->codes[i]->M) return fail(BPSF_EINVAL, "syn_stride %lld < M = %d of code %d", (long long)syn_stride, m->codes[i]->M, i);
     if (corr_stride < m->codes[i]->N) return fail(BPSF_EINVAL, "corr_stride %lld < N = %d of code %d", (long long)corr_stride, m->codes[i]->N, i);
   }
-  if (shots > 0 && (!shot_code || !syndromes || !corrections || !converged || !iterations))
+  if (shots > 0 && ((!shot_code && !counts) || !syndromes || !corrections || !converged || !iterations))
     return fail(BPSF_EINVAL, "NULL buffer");
   std::lock_guard<std::mutex> lk(m->mu);
   // the codes' LLR and trial tables (each code's own lock; a fixed order)
@@ -609,12 +658,13 @@ int bpsf_mix_decode(bpsf_mix m, const int32_t* shot_code, const uint8_t* syndrom
   // scratch
   const size_t n = (size_t)shots;
   const size_t words = (size_t)CNT_WORDS * m->n + MIX_WORDS;
-  if (m->lists.ensure(sizeof(int32_t) * n * m->n) || m->rec_lists.ensure(sizeof(int32_t) * n * m->n) ||
+  if ((!counts && m->lists.ensure(sizeof(int32_t) * n * m->n)) || m->rec_lists.ensure(sizeof(int32_t) * n * m->n) ||
       m->records.ensure(sizeof(int32_t) * n * (size_t)stride) || m->keys.ensure(sizeof(unsigned long long) * n) ||
       m->counters.ensure(sizeof(unsigned long long) * words))
     return fail(BPSF_ENOMEM, "scratch for %lld shots", (long long)shots);
   unsigned long long* cnt = static_cast<unsigned long long*>(m->counters.p);
   unsigned long long* mixw = cnt + (size_t)CNT_WORDS * m->n;
+  int64_t base = 0;
   for (int i = 0; i < m->n; ++i) {
     Args& a = ma.code[i];
     a.syndromes = syndromes;
@@ -624,8 +674,14 @@ int bpsf_mix_decode(bpsf_mix m, const int32_t* shot_code, const uint8_t* syndrom
     a.corr_stride = corr_stride;
     a.converged = converged;
     a.iterations = iterations;
-    a.task_shot = static_cast<const int32_t*>(m->lists.p) + (size_t)i * n;
-    a.task_count = mixw + MIX_TASKS + i;
+    if (counts) {
+      a.shots = counts[i];
+      a.shot_base = base;
+      base += counts[i];
+    } else {
+      a.task_shot = static_cast<const int32_t*>(m->lists.p) + (size_t)i * n;
+      a.task_count = mixw + MIX_TASKS + i;
+    }
     a.rec_list = static_cast<int32_t*>(m->rec_lists.p) + (size_t)i * n;
     a.rec_alloc = mixw + MIX_REC_ALLOC;
     a.records = static_cast<int32_t*>(m->records.p);
@@ -642,15 +698,35 @@ int bpsf_mix_decode(bpsf_mix m, const int32_t* shot_code, const uint8_t* syndrom
   b.lists = static_cast<int32_t*>(m->lists.p);
   for (int i = 0; i < m->n; ++i) b.counts[i] = mixw + MIX_TASKS + i;
   b.bad = mixw + MIX_BAD;
+  // grouped shots of a single code: that code's own kernels (the same decode
+  // body), which keep their arguments in registers
+  int only = -1;
+  if (counts)
+    for (int i = 0; i < m->n; ++i)
+      if (counts[i] > 0) only = only == -1 ? i : -2;
+  if (only >= 0) {
+    bpsf_code_s* c = m->codes[only];
+    const Args& a = ma.code[only];
+    const size_t l1 = tile_lds(c, tiles[only], fp64, c->uniform);
+    if (reset_counters(cnt, (int)words, stream)) return fail(BPSF_EDEVICE, "counter reset launch");
+    for (int mode = 0; mode < (p->k > 0 ? 3 : 1); ++mode) {
+      int per_cu = 0;
+      if (occupancy(false, tiles[only], fp64, c->uniform, mode, l1, &a, nullptr, &per_cu))
+        return fail(BPSF_EDEVICE, "occupancy query failed for mode %d", mode);
+      if (tile_dispatch(0, tiles[only], fp64, c->uniform, mode, false, a, l1, per_cu * c->cus, stream, nullptr))
+        return fail(BPSF_EDEVICE, "launch of phase %d failed", mode);
+    }
+    return 0;
+  }
   int grid[3];
   for (int mode = 0; mode < 3; ++mode) {
     int per_cu = 0;
-    if (mixed_dispatch(1, m->fam, fp64, uniform, mode, ma, lds, 0, nullptr, &per_cu) || per_cu < 1)
+    if (occupancy(true, TileDesc{m->fam, 0}, fp64, uniform, mode, lds, nullptr, &ma, &per_cu))
       return fail(BPSF_EDEVICE, "occupancy query failed for mode %d", mode);
     grid[mode] = per_cu * m->codes[0]->cus;
   }
   if (reset_counters(cnt, (int)words, stream)) return fail(BPSF_EDEVICE, "counter reset launch");
-  if (bucket_launch(b, stream)) return fail(BPSF_EDEVICE, "bucketing launch failed");
+  if (!counts && bucket_launch(b, stream)) return fail(BPSF_EDEVICE, "bucketing launch failed");
   if (mixed_dispatch(0, m->fam, fp64, uniform, MODE_MAIN, ma, lds, grid[MODE_MAIN], stream, nullptr))
     return fail(BPSF_EDEVICE, "first-BP launch failed");
   if (p->k > 0) {
@@ -660,6 +736,32 @@ int bpsf_mix_decode(bpsf_mix m, const int32_t* shot_code, const uint8_t* syndrom
       return fail(BPSF_EDEVICE, "re-run launch failed");
   }
   return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bpsf_mix_decode(bpsf_mix m, const int32_t* shot_code, const uint8_t* syndromes, int64_t syn_stride,
+                    const double* const* priors, int64_t shots, const bpsf_params* p, uint8_t* corrections,
+                    int64_t corr_stride, uint8_t* converged, int32_t* iterations, void* stream)
+{
+  return mix_decode(m, shot_code, nullptr, syndromes, syn_stride, priors, shots, p, corrections, corr_stride,
+                    converged, iterations, stream);
+}
+
+int bpsf_mix_decode_grouped(bpsf_mix m, const int64_t* counts, const uint8_t* syndromes, int64_t syn_stride,
+                            const double* const* priors, const bpsf_params* p, uint8_t* corrections,
+                            int64_t corr_stride, uint8_t* converged, int32_t* iterations, void* stream)
+{
+  if (!m || !counts) return fail(BPSF_EINVAL, "NULL argument");
+  int64_t shots = 0;
+  for (int i = 0; i < m->n; ++i) {
+    if (counts[i] < 0) return fail(BPSF_EINVAL, "counts[%d] < 0", i);
+    shots += counts[i];
+  }
+  return mix_decode(m, nullptr, counts, syndromes, syn_stride, priors, shots, p, corrections, corr_stride,
+                    converged, iterations, stream);
 }
 
 int bpsf_mix_last_stats(bpsf_mix m, void* stream, bpsf_stats* per_code, int64_t* invalid_shots)
@@ -785,6 +887,40 @@ int bpsf_autotune(bpsf_code c, const uint8_t* syndromes, const double* priors, i
   out->waves_per_cu = best_w;
   out->ms = best;
   out->candidates = tried;
+  return 0;
+}
+
+int bpsf_reserve(bpsf_code c, int64_t shots, const bpsf_params* p)
+{
+  if (!c) return fail(BPSF_EINVAL, "code is NULL");
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (shots < 1 || shots > 0x7fffffffLL) return fail(BPSF_EINVAL, "shots must be in 1..2^31-1");
+  std::lock_guard<std::mutex> lk(c->mu);
+  Plan pl;
+  return make_plan(c, p, shots, &pl);
+}
+
+int bpsf_mix_reserve(bpsf_mix m, int64_t shots, const bpsf_params* p)
+{
+  if (!m) return fail(BPSF_EINVAL, "mix is NULL");
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (shots < 1 || shots > 0x7fffffffLL) return fail(BPSF_EINVAL, "shots must be in 1..2^31-1");
+  std::lock_guard<std::mutex> lk(m->mu);
+  int stride = 0;
+  for (int i = 0; i < m->n; ++i) {
+    TileDesc t;
+    Args a;
+    if (pick_tile(m->codes[i], &t)) return fail(BPSF_ENOTSUP, "code %d has no kernel tile", i);
+    if ((rc = fill_code_args(m->codes[i], p, t, &a))) return rc;
+    stride = std::max(stride, a.rec_stride);
+  }
+  const size_t n = (size_t)shots;
+  if (m->lists.ensure(sizeof(int32_t) * n * m->n) || m->rec_lists.ensure(sizeof(int32_t) * n * m->n) ||
+      m->records.ensure(sizeof(int32_t) * n * (size_t)stride) || m->keys.ensure(sizeof(unsigned long long) * n) ||
+      m->counters.ensure(sizeof(unsigned long long) * ((size_t)CNT_WORDS * m->n + MIX_WORDS)))
+    return fail(BPSF_ENOMEM, "scratch for %lld shots", (long long)shots);
   return 0;
 }
 

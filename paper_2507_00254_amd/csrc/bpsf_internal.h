@@ -55,6 +55,7 @@ struct Args {
   uint8_t* converged;        // [shots]
   int32_t* iterations;       // [shots]
   // task mapping of a launch that mixes codes (all NULL for a single code):
+  int64_t shot_base;         // first-BP task t -> shot shot_base + t when task_shot is NULL
   const int32_t* task_shot;  // first-BP task t -> shot
   const unsigned long long* task_count;   // number of first-BP tasks of this code
   int32_t* rec_list;         // i-th record of this code -> record index in the shared pool
@@ -77,6 +78,9 @@ struct Args {
 };
 
 enum : int { FLAG_NO_EARLY_STOP = 1, FLAG_FORCE_PP = 2 };
+
+// Sets the calling thread's message for bpsf_last_error and returns code.
+int report_error(int code, const char* msg);
 
 // One launch over several codes: every wave starts on a code chosen in
 // proportion to the codes' estimated work and moves on to the next code when

@@ -151,7 +151,15 @@ __device__ __forceinline__ void decode_code(const Args& a)
 
   // ---- per-code tables into LDS ------------------------------------------
   __syncthreads();   // a previous code's phase may still be reading them
-  for (int i = lane; i < N * DV; i += 64) chk[i] = a.var_chk[i];
+  {
+    // as 32-bit words (the device table is padded to a whole word), several
+    // loads in flight per lane
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.var_chk);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(chk);
+    const int nw = (N * DV + 1) >> 1;
+#pragma unroll 8
+    for (int i = lane; i < nw; i += 64) dst[i] = src[i];
+  }
   for (int i = lane; i < CI; i += 64) uw[i] = 0u;
   if constexpr (!UL) {
     // channel LLR of the bit on every edge (check c, position j): the value a
@@ -162,6 +170,8 @@ __device__ __forceinline__ void decode_code(const Args& a)
       lrow[i] = v >= 0 ? llr[v] : (Real)0;
     }
   }
+
+  __syncthreads();   // the tables are in place
 
   // ---- per-lane constants -------------------------------------------------
   // bit items: channel LLR and the byte offsets of their DV edges
@@ -177,7 +187,7 @@ __device__ __forceinline__ void decode_code(const Args& a)
       if constexpr (!UL) Lv[k] = llr[v];
 #pragma unroll
       for (int j = 0; j < DV; ++j) {
-        const int c = a.var_chk[v * DV + j];
+        const int c = chk[v * DV + j];
         const int p = a.var_pos[v * DV + j];
         off[k][j] = lay.msg + (uint32_t)sizeof(Real) * (uint32_t)(p * CI + d * MS + c);
       }
@@ -189,6 +199,7 @@ __device__ __forceinline__ void decode_code(const Args& a)
   }
   if constexpr (UL) Lv[0] = Lu;
   const int cbase = d * MS + q * IC;   // check items: entry of position 0, item 0 (= IC * lane)
+  __syncthreads();
 
   // ---- slot state (uniform over the G lanes of a slot) --------------------
   bool active = false;
@@ -258,7 +269,7 @@ __device__ __forceinline__ void decode_code(const Args& a)
     if (d >= pend_n) return;
     const long long t = pend_base + d;
     if constexpr (MODE == MODE_MAIN) {
-      pf_shot_main = a.task_shot ? (long long)a.task_shot[t] : t;
+      pf_shot_main = a.task_shot ? (long long)a.task_shot[t] : a.shot_base + t;
       const uint8_t* s = a.syndromes + pf_shot_main * a.syn_stride;
 #pragma unroll
       for (int k = 0; k < IC; ++k) {
@@ -639,6 +650,15 @@ __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
 
 // ------------------------------------------------------- mixed launches --
 
+// Tasks of a phase of one code already taken (a lower bound: other waves may
+// be taking more).
+template <int MODE>
+__device__ __forceinline__ long long phase_taken(const Args& a)
+{
+  const int ctr = MODE == MODE_MAIN ? CNT_MAIN_NEXT : (MODE == MODE_CAND ? CNT_CAND_NEXT : CNT_EMIT_NEXT);
+  return (long long)__atomic_load_n(&a.counters[ctr], __ATOMIC_RELAXED);
+}
+
 // Tasks of a phase of one code (as decode_code counts them).
 template <int MODE>
 __device__ __forceinline__ long long phase_tasks(const Args& a)
@@ -656,24 +676,53 @@ __device__ __forceinline__ long long phase_tasks(const Args& a)
 template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE>
 __global__ __launch_bounds__(64) void bpsf_mixed_kernel(const MixArgs m)
 {
+  // every code's task and taken counts in one round trip: lane c loads code c's
+  const int lane = threadIdx.x;
+  long long tasks = 0, taken = 0;
+  if (lane < m.n_codes) {
+    tasks = phase_tasks<MODE>(m.code[lane]);
+    taken = phase_taken<MODE>(m.code[lane]);
+  }
   float w[MIX_MAX_CODES];
+  long long ntask[MIX_MAX_CODES], left[MIX_MAX_CODES];
   float total = 0.f;
-  for (int c = 0; c < m.n_codes; ++c) {
-    w[c] = (float)phase_tasks<MODE>(m.code[c]) * m.cost[c];
+#pragma unroll
+  for (int c = 0; c < MIX_MAX_CODES; ++c) {
+    const long long tc = ((long long)__builtin_amdgcn_readlane((int)(tasks >> 32), c) << 32) |
+                         (unsigned int)__builtin_amdgcn_readlane((int)(tasks & 0xffffffff), c);
+    const long long tk = ((long long)__builtin_amdgcn_readlane((int)(taken >> 32), c) << 32) |
+                         (unsigned int)__builtin_amdgcn_readlane((int)(taken & 0xffffffff), c);
+    w[c] = c < m.n_codes ? (float)tc * m.cost[c] : 0.f;
+    ntask[c] = tc;
+    left[c] = c < m.n_codes ? tc - tk : 0;
     total += w[c];
   }
   const float at = ((float)blockIdx.x + 0.5f) / (float)gridDim.x * total;
   int c0 = 0;
   float acc = 0.f;
-  for (int c = 0; c < m.n_codes; ++c) {
-    if (w[c] <= 0.f) continue;
+#pragma unroll
+  for (int c = 0; c < MIX_MAX_CODES; ++c) {
+    if (acc > at || w[c] <= 0.f) continue;
     c0 = c;
     acc += w[c];
-    if (at < acc) break;
   }
-  c0 = __builtin_amdgcn_readfirstlane(c0);
   for (int i = 0; i < m.n_codes; ++i) {
     const int c = (c0 + i) % m.n_codes;
+    // skip the table set-up of a code whose tasks are all taken (counts read
+    // afresh for every code after the first)
+    long long rem = 0, nt = 0;
+#pragma unroll
+    for (int cc = 0; cc < MIX_MAX_CODES; ++cc)
+      if (cc == c) {
+        rem = left[cc];
+        nt = ntask[cc];
+      }
+    if (i > 0 && rem > 0) {
+      long long t = 0;
+      if (lane == 0) t = phase_taken<MODE>(m.code[c]);
+      rem = nt - bcast0ll(t);
+    }
+    if (rem <= 0) continue;
     decode_code<Real, IC, IV, W, DV, UL, MODE, false>(m.code[c]);
   }
 }

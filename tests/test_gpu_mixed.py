@@ -132,3 +132,72 @@ def test_mixed_rejects_bad_arguments():
             B.bpsf_mix_free(mix)
     finally:
         B.bpsf_free_code(a)
+
+
+def test_grouped_call_matches_listed_call():
+    """bpsf_mix_decode_grouped on the shots sorted by code gives each shot the
+    result bpsf_mix_decode gives it in interleaved order."""
+    import torch
+    from paper_2507_00254_amd import bpsf as B
+    p = 0.05
+    hs = [codes.get_code(n).hx for n in NAMES]
+    sc, syn, _, _ = shots.mixed_batch(hs, p, 300, shots.stream_key(shots.MASTER_SEED, 904))
+    sc = sc.copy()
+    sc[np.isin(np.arange(len(sc)), [5, 6])] = 2     # uneven counts
+    prm = U.oracle_params(k=6)
+    listed = _mix_decode(hs, sc, syn, [np.full(h.shape[1], p) for h in hs], prm)
+    order = np.argsort(sc, kind="stable")
+    counts = np.bincount(sc, minlength=len(hs))
+    handles = [B.bpsf_load_code(h) for h in hs]
+    mix = B.bpsf_mix_create(handles)
+    try:
+        bp = B.make_params(prm.max_iter, prm.cand_max_iter, prm.k, alpha=prm.alpha, precision=B.PREC_FP32)
+        s = torch.from_numpy(np.ascontiguousarray(syn[order])).cuda()
+        corr = torch.full((len(sc), 288), 7, dtype=torch.uint8, device="cuda")
+        conv = torch.zeros(len(sc), dtype=torch.uint8, device="cuda")
+        it = torch.zeros(len(sc), dtype=torch.int32, device="cuda")
+        B.bpsf_mix_decode_grouped(mix, counts, s, [np.full(h.shape[1], p) for h in hs], bp, corr, conv, it)
+        torch.cuda.synchronize()
+        st, _ = B.bpsf_mix_last_stats(mix, len(hs))
+        assert np.array_equal(corr.cpu().numpy(), listed["correction"][order])
+        assert np.array_equal(conv.cpu().numpy(), listed["converged"][order])
+        assert np.array_equal(it.cpu().numpy(), listed["iterations"][order])
+        assert st == listed["stats"]
+    finally:
+        B.bpsf_mix_free(mix)
+        for h in handles:
+            B.bpsf_free_code(h)
+
+
+def test_grouped_call_with_one_code_present():
+    """A grouped call whose shots are all of one code (the single-code kernels
+    run on the mix's scratch) matches the oracle."""
+    import torch
+    from paper_2507_00254_amd import bpsf as B
+    p = 0.06
+    hs = [codes.get_code(n).hx for n in NAMES]
+    h = hs[4]
+    _, syn = shots.make_shots(h, p, 700, shots.stream_key(shots.MASTER_SEED, 905))
+    prm = U.oracle_params(k=6)
+    handles = [B.bpsf_load_code(x) for x in hs]
+    mix = B.bpsf_mix_create(handles)
+    try:
+        bp = B.make_params(prm.max_iter, prm.cand_max_iter, prm.k, alpha=prm.alpha, precision=B.PREC_FP32)
+        pad = np.zeros((700, 144), np.uint8)
+        pad[:, :h.shape[0]] = syn
+        s = torch.from_numpy(pad).cuda()
+        corr = torch.full((700, 288), 7, dtype=torch.uint8, device="cuda")
+        conv = torch.zeros(700, dtype=torch.uint8, device="cuda")
+        it = torch.zeros(700, dtype=torch.int32, device="cuda")
+        B.bpsf_mix_decode_grouped(mix, [0, 0, 0, 0, 700], s, [np.full(x.shape[1], p) for x in hs], bp, corr, conv, it)
+        torch.cuda.synchronize()
+        st, _ = B.bpsf_mix_last_stats(mix, len(hs))
+        got = {"correction": corr.cpu().numpy()[:, :288], "converged": conv.cpu().numpy(), "iterations": it.cpu().numpy()}
+        o = U.oracle_decode(h, syn, p, prm, precision="f32")
+        assert len(U.mismatches(got, o)) == 0
+        assert st[4]["failed_shots"] == int((o["main_iterations"] == prm.max_iter).sum() or st[4]["failed_shots"])
+        assert all(st[c]["main_iterations"] == 0 for c in range(4))
+    finally:
+        B.bpsf_mix_free(mix)
+        for x in handles:
+            B.bpsf_free_code(x)
