@@ -727,28 +727,60 @@ __global__ __launch_bounds__(64) void bpsf_mixed_kernel(const MixArgs m)
   }
 }
 
-__global__ void bpsf_bucket_kernel(BucketArgs b)
+// Each block takes a contiguous slice of the shots: it counts the slice's
+// shots of every code in LDS, reserves each code's range of the lists with
+// one global atomic, then places the shots (one LDS atomic per wave and code
+// in both passes). Order inside a code's list is arbitrary; results do not
+// depend on it.
+__global__ __launch_bounds__(256) void bpsf_bucket_kernel(BucketArgs b)
 {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  int c = -1;
-  if (i < b.shots) {
-    c = b.shot_code[i];
-    if (c < 0 || c >= b.n_codes) {
-      atomicAdd(b.bad, 1ull);
-      c = -1;
+  __shared__ unsigned int cnt[MIX_MAX_CODES];
+  __shared__ unsigned long long base[MIX_MAX_CODES];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const long long per = (b.shots + gridDim.x - 1) / gridDim.x;
+  const long long lo = (long long)blockIdx.x * per;
+  const long long hi = lo + per < b.shots ? lo + per : b.shots;
+  if (tid < MIX_MAX_CODES) cnt[tid] = 0u;
+  __syncthreads();
+  for (long long i0 = lo; i0 < hi; i0 += blockDim.x) {
+    const long long i = i0 + tid;
+    int c = -1;
+    if (i < hi) {
+      c = b.shot_code[i];
+      if (c < 0 || c >= b.n_codes) {
+        atomicAdd(b.bad, 1ull);
+        c = -1;
+      }
+    }
+    for (int cc = 0; cc < b.n_codes; ++cc) {
+      const unsigned long long mine = __ballot(c == cc);
+      if (mine != 0ull && lane == __ffsll((long long)mine) - 1) atomicAdd(&cnt[cc], (unsigned)__popcll(mine));
     }
   }
-  // one counter update per (wave, code)
-  for (int cc = 0; cc < b.n_codes; ++cc) {
-    const unsigned long long mine = __ballot(c == cc);
-    if (mine == 0ull) continue;
-    const int leader = __ffsll((long long)mine) - 1;
-    unsigned long long base = 0;
-    if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(b.counts[cc], (unsigned long long)__popcll(mine));
-    base = __shfl(base, leader);
-    if (c == cc) {
-      const int rank = __popcll(mine & ((1ull << (threadIdx.x & 63)) - 1ull));
-      b.lists[(long long)cc * b.shots + (long long)(base + rank)] = (int32_t)i;
+  __syncthreads();
+  if (tid < b.n_codes) {
+    base[tid] = cnt[tid] ? atomicAdd(b.counts[tid], (unsigned long long)cnt[tid]) : 0ull;
+    cnt[tid] = 0u;
+  }
+  __syncthreads();
+  for (long long i0 = lo; i0 < hi; i0 += blockDim.x) {
+    const long long i = i0 + tid;
+    int c = -1;
+    if (i < hi) {
+      c = b.shot_code[i];
+      if (c < 0 || c >= b.n_codes) c = -1;
+    }
+    for (int cc = 0; cc < b.n_codes; ++cc) {
+      const unsigned long long mine = __ballot(c == cc);
+      if (mine == 0ull) continue;
+      const int leader = __ffsll((long long)mine) - 1;
+      unsigned int first = 0;
+      if (lane == leader) first = atomicAdd(&cnt[cc], (unsigned)__popcll(mine));
+      first = __shfl(first, leader);
+      if (c == cc) {
+        const unsigned int rank = (unsigned)__popcll(mine & ((1ull << lane) - 1ull));
+        b.lists[(long long)cc * b.shots + (long long)(base[cc] + first + rank)] = (int32_t)i;
+      }
     }
   }
 }
@@ -858,7 +890,9 @@ int mixed_dispatch(int what, int fam, bool fp64, bool ul, int mode, const MixArg
 int bucket_launch(const BucketArgs& b, void* stream)
 {
   if (b.shots <= 0) return 0;
-  const long long blocks = (b.shots + 255) / 256;
+  // slices of at least 8192 shots, at most 2048 blocks
+  long long blocks = (b.shots + 8191) / 8192;
+  if (blocks > 2048) blocks = 2048;
   hipLaunchKernelGGL(bpsf_bucket_kernel, dim3((unsigned)blocks), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), b);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
