@@ -86,9 +86,11 @@ typedef struct {
  * graph of H (Section II-B): bits are columns, checks are rows. Builds the
  * device tables (edge layouts) on the current device; *out receives a handle
  * to free with bpsf_free_code. Fails with BPSF_ENOTSUP when the row and column
- * weights have no compiled kernel tile (currently regular codes, row weight 6,
- * column weight 3, up to 288 bits, e.g. the bivariate-bicycle codes of
- * Appendix A).
+ * weights have no compiled kernel family: currently regular codes with row
+ * weight 6 and column weight 3 of up to 576 checks and 1152 bits (the
+ * bivariate-bicycle and coprime-BB codes of Appendix A), and with row weight
+ * 10 and column weight 5 of up to 576 checks and 576 bits (the
+ * generalized-bicycle code of Appendix A).
  */
 int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, int32_t N, bpsf_code* out);
 

@@ -29,9 +29,12 @@ struct Family {
   static_assert(W >= 2 && DV >= 1, "row weight >= 2");
 };
 
-// Compiled families (IC, IV, W, DV).
+// Compiled families (IC, IV, W, DV): row weight 6 / column weight 3 (the
+// bivariate-bicycle and coprime-BB codes), row weight 10 / column weight 5
+// (the generalized-bicycle code of Appendix A).
 #define BPSF_FAMILY_LIST(X) \
-  X(9, 18, 6, 3)
+  X(9, 18, 6, 3)            \
+  X(9, 9, 10, 5)
 
 constexpr int MAX_D = 16;
 
