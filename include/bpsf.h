@@ -44,6 +44,8 @@ extern "C" {
 /* Trial vector sets (Algorithm 1, combinations(Phi, w_max)). */
 #define BPSF_TRIALS_ALL_SUBSETS 0   /* all 2^k subsets of Phi; trial index = mask, bit j <-> Phi[j] */
 #define BPSF_TRIALS_WEIGHT_LE 1     /* subsets of weight 1..w_max, by weight, then combination order */
+#define BPSF_TRIALS_TABLE 2         /* the caller's list (bpsf_set_trial_table), e.g. n_s sampled
+                                       subsets per weight 1..w_max as in Section IV */
 
 /* Result selection among successful trials (Section IV). */
 #define BPSF_SELECT_MIN_WEIGHT 0    /* lightest e' + t; ties to the lower trial index */
@@ -52,6 +54,9 @@ extern "C" {
 /* bpsf_params.flags (test and study options) */
 #define BPSF_FLAG_NO_EARLY_STOP 1   /* run max_iter iterations even after e H^T = s */
 #define BPSF_FLAG_FORCE_PP 2        /* run the trials even when the first BP succeeded */
+#define BPSF_FLAG_PRUNE 4           /* with BPSF_SELECT_FIRST only: a trial is skipped, or stopped,
+                                       once a lower-index trial of its shot has succeeded (the
+                                       result is the same; fewer trial iterations run) */
 
 #define BPSF_PREC_FP32 0            /* messages in float */
 #define BPSF_PREC_FP64 1            /* messages in double */
@@ -286,6 +291,17 @@ int bpsf_server_replay(bpsf_server server, int64_t n_requests, const double* arr
                        double* wall_s);
 int bpsf_server_counters(bpsf_server server, int64_t* batches, int64_t* batch_shots, int64_t* requests_done);
 int bpsf_server_destroy(bpsf_server server);
+
+/*
+ * Trial list for params.cand_mode = BPSF_TRIALS_TABLE on this handle:
+ * masks (device uint32, owned by the caller, valid while such decodes run)
+ * holds n_trials (1..2^31-1) k-bit masks in trial order, bit j <-> Phi[j]
+ * (bits at or above k are ignored); shot i uses masks[i * stride + t], so
+ * stride 0 gives every shot the same list and stride n_trials one list per
+ * shot (in a mixed call i is the shot's row in the call). masks = NULL
+ * clears the list. Takes effect on later calls.
+ */
+int bpsf_set_trial_table(bpsf_code code, const uint32_t* masks, int64_t n_trials, int64_t stride);
 
 /* Shape of a loaded code: M, N, edges, row weight, column weight (host outs, any may be NULL). */
 int bpsf_code_info(bpsf_code code, int32_t* M, int32_t* N, int32_t* edges, int32_t* row_weight,

@@ -489,7 +489,7 @@ typedef struct {
     const real *L;
     const oracle_params *prm;
     const uint32_t *masks;
-    int64_t n_trials, lo, hi;
+    int64_t n_trials, mask_stride, lo, hi;
     uint8_t *corr, *conv;
     int32_t *iters, *winner, *phi, *main_iters;
     int64_t *trial_iters;
@@ -509,7 +509,8 @@ static void *batch_worker(void *arg)
     for (int64_t i = j->lo; i < j->hi; i++) {
         shot_result res;
         int32_t phi_tmp[32];
-        if (bpsf_one(j->g, j->syn + (size_t)i * M, j->L, j->prm, j->masks, j->n_trials, &w, s2, best,
+        if (bpsf_one(j->g, j->syn + (size_t)i * M, j->L, j->prm, j->masks + i * j->mask_stride, j->n_trials,
+                     &w, s2, best,
                      j->corr + (size_t)i * N, phi_tmp, NULL, NULL, NULL, &res)) { j->rc = -1; break; }
         j->conv[i] = res.converged;
         j->iters[i] = res.iterations;
@@ -522,6 +523,34 @@ static void *batch_worker(void *arg)
     free(s2);
     free(best);
     return NULL;
+}
+
+static int run_batch(const graph *g, const uint8_t *syndromes, int64_t shots, const real *L,
+                     const oracle_params *prm, const uint32_t *masks, int64_t nt, int64_t mask_stride,
+                     uint8_t *corr, uint8_t *conv, int32_t *iters, int32_t *winner, int32_t *phi,
+                     int32_t *main_iters, int64_t *trial_iters, int32_t nthreads)
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if ((int64_t)nthreads > shots) nthreads = (int32_t)shots;
+    batch_job jobs[256];
+    pthread_t tid[256];
+    for (int t = 0; t < nthreads; t++) {
+        batch_job *j = &jobs[t];
+        j->g = g; j->syn = syndromes; j->L = L; j->prm = prm; j->masks = masks; j->n_trials = nt;
+        j->mask_stride = mask_stride;
+        j->lo = shots * t / nthreads; j->hi = shots * (t + 1) / nthreads;
+        j->corr = corr; j->conv = conv; j->iters = iters; j->winner = winner; j->phi = phi;
+        j->main_iters = main_iters; j->trial_iters = trial_iters; j->rc = 0;
+    }
+    int started = 0;
+    for (int t = 1; t < nthreads; t++)
+        if (pthread_create(&tid[t], NULL, batch_worker, &jobs[t]) == 0) started = t; else { jobs[t].rc = -1; break; }
+    batch_worker(&jobs[0]);
+    for (int t = 1; t <= started; t++) pthread_join(tid[t], NULL);
+    int rc = 0;
+    for (int t = 0; t < nthreads; t++) if (jobs[t].rc) rc = -1;
+    return rc;
 }
 
 /* BP-SF over a batch of syndromes; shots are split statically over threads. */
@@ -541,27 +570,38 @@ int FN(oracle_bpsf_batch)(int32_t M, int32_t N, const int32_t *row_ptr, const in
     int rc = -1;
     if (masks && L && priors_to_llr(priors, N, L) == 0) {
         trial_masks(prm, masks);
-        if (nthreads < 1) nthreads = 1;
-        if (nthreads > 256) nthreads = 256;
-        if ((int64_t)nthreads > shots) nthreads = (int32_t)shots;
-        batch_job jobs[256];
-        pthread_t tid[256];
-        for (int t = 0; t < nthreads; t++) {
-            batch_job *j = &jobs[t];
-            j->g = &g; j->syn = syndromes; j->L = L; j->prm = prm; j->masks = masks; j->n_trials = nt;
-            j->lo = shots * t / nthreads; j->hi = shots * (t + 1) / nthreads;
-            j->corr = corr; j->conv = conv; j->iters = iters; j->winner = winner; j->phi = phi;
-            j->main_iters = main_iters; j->trial_iters = trial_iters; j->rc = 0;
-        }
-        int started = 0;
-        for (int t = 1; t < nthreads; t++)
-            if (pthread_create(&tid[t], NULL, batch_worker, &jobs[t]) == 0) started = t; else { jobs[t].rc = -1; break; }
-        batch_worker(&jobs[0]);
-        for (int t = 1; t <= started; t++) pthread_join(tid[t], NULL);
-        rc = 0;
-        for (int t = 0; t < nthreads; t++) if (jobs[t].rc) rc = -1;
+        rc = run_batch(&g, syndromes, shots, L, prm, masks, nt, 0, corr, conv, iters, winner, phi, main_iters,
+                       trial_iters, nthreads);
     }
     free(masks);
+    free(L);
+    graph_free(&g);
+    return rc;
+}
+
+/* As oracle_bpsf_batch with the trial vectors given by the caller instead of
+ * prm->cand_mode: shot i tries masks[i * mask_stride + t] for t < n_trials,
+ * in that order (bit j <-> Phi[j]; bits at or above k are ignored). A stride
+ * of 0 gives every shot the same list. */
+int FN(oracle_bpsf_batch_table)(int32_t M, int32_t N, const int32_t *row_ptr, const int32_t *col_idx,
+                                const uint8_t *syndromes, int64_t shots, const double *priors,
+                                const oracle_params *prm, const uint32_t *masks, int64_t n_trials,
+                                int64_t mask_stride, uint8_t *corr, uint8_t *conv, int32_t *iters,
+                                int32_t *winner, int32_t *phi, int32_t *main_iters, int64_t *trial_iters,
+                                int32_t nthreads)
+{
+    oracle_params q = *prm;
+    q.cand_mode = 0;   /* validated as such; the list comes from the caller */
+    if (M < 0 || N < 0 || shots < 0 || !row_ptr || check_params(&q, N)) return -1;
+    if (n_trials < 0 || mask_stride < 0 || (n_trials > 0 && !masks)) return -1;
+    if (shots == 0) return 0;
+    graph g;
+    if (graph_build(&g, M, N, row_ptr, col_idx)) return -1;
+    real *L = (real *)malloc(sizeof(real) * (size_t)(N > 0 ? N : 1));
+    int rc = -1;
+    if (L && priors_to_llr(priors, N, L) == 0)
+        rc = run_batch(&g, syndromes, shots, L, prm, masks, n_trials, mask_stride, corr, conv, iters, winner, phi,
+                       main_iters, trial_iters, nthreads);
     free(L);
     graph_free(&g);
     return rc;

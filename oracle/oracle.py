@@ -164,8 +164,12 @@ class OracleLib:
                 "main_converged": int(summ[3]), "winner": int(summ[4]),
                 "trial_iteration_total": ttot.value}
 
-    def bpsf_batch(self, h, syndromes, priors, params: Params, prec: str = "f64", threads: int = 1):
-        """BP-SF over a batch of syndromes ``[shots, M]``; shots split over threads."""
+    def bpsf_batch(self, h, syndromes, priors, params: Params, prec: str = "f64", threads: int = 1,
+                   masks=None):
+        """BP-SF over a batch of syndromes ``[shots, M]``; shots split over threads.
+        ``masks``: trial vectors given by the caller instead of
+        ``params.cand_mode``, either ``[n_trials]`` (every shot) or
+        ``[shots, n_trials]`` (one list per shot)."""
         row_ptr, col_idx, m, n = _csr(h)
         syn = np.ascontiguousarray(syndromes, dtype=np.uint8)
         if syn.ndim != 2 or syn.shape[1] != m:
@@ -181,12 +185,25 @@ class OracleLib:
         main_it = np.zeros(shots, np.int32)
         trial_it = np.zeros(shots, np.int64)
         prm = params.c()
-        fn = getattr(self.lib(prec), f"oracle_bpsf_batch_{prec}")
-        rc = fn(C.c_int32(m), C.c_int32(n), _ptr(row_ptr, C.c_int32), _ptr(col_idx, C.c_int32),
-                _ptr(syn, C.c_uint8), C.c_int64(shots), _ptr(p, C.c_double), C.byref(prm),
-                _ptr(corr, C.c_uint8), _ptr(conv, C.c_uint8), _ptr(iters, C.c_int32),
+        outs = (_ptr(corr, C.c_uint8), _ptr(conv, C.c_uint8), _ptr(iters, C.c_int32),
                 _ptr(winner, C.c_int32), _ptr(phi, C.c_int32), _ptr(main_it, C.c_int32),
                 _ptr(trial_it, C.c_int64), C.c_int32(threads))
+        if masks is None:
+            fn = getattr(self.lib(prec), f"oracle_bpsf_batch_{prec}")
+            rc = fn(C.c_int32(m), C.c_int32(n), _ptr(row_ptr, C.c_int32), _ptr(col_idx, C.c_int32),
+                    _ptr(syn, C.c_uint8), C.c_int64(shots), _ptr(p, C.c_double), C.byref(prm), *outs)
+        else:
+            tab = np.ascontiguousarray(masks, dtype=np.uint32)
+            if tab.ndim == 1:
+                nt, stride = tab.shape[0], 0
+            elif tab.ndim == 2 and tab.shape[0] == shots:
+                nt, stride = tab.shape[1], tab.shape[1]
+            else:
+                raise ValueError("masks must be [n_trials] or [shots, n_trials]")
+            fn = getattr(self.lib(prec), f"oracle_bpsf_batch_table_{prec}")
+            rc = fn(C.c_int32(m), C.c_int32(n), _ptr(row_ptr, C.c_int32), _ptr(col_idx, C.c_int32),
+                    _ptr(syn, C.c_uint8), C.c_int64(shots), _ptr(p, C.c_double), C.byref(prm),
+                    _ptr(tab, C.c_uint32), C.c_int64(nt), C.c_int64(stride), *outs)
         if rc != 0:
             raise ValueError("oracle_bpsf_batch rejected its arguments")
         return {"correction": corr, "converged": conv, "iterations": iters, "winner": winner,

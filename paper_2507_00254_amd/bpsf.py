@@ -16,9 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbpsf.so")
 
 BPSF_OK, BPSF_EINVAL, BPSF_ENOMEM, BPSF_ENOTSUP, BPSF_EDEVICE = 0, -1, -2, -3, -4
-TRIALS_ALL_SUBSETS, TRIALS_WEIGHT_LE = 0, 1
+TRIALS_ALL_SUBSETS, TRIALS_WEIGHT_LE, TRIALS_TABLE = 0, 1, 2
 SELECT_MIN_WEIGHT, SELECT_FIRST = 0, 1
-FLAG_NO_EARLY_STOP, FLAG_FORCE_PP = 1, 2
+FLAG_NO_EARLY_STOP, FLAG_FORCE_PP, FLAG_PRUNE = 1, 2, 4
 PREC_FP32, PREC_FP64 = 0, 1
 
 
@@ -69,6 +69,7 @@ def _load():
     lib.bpsf_code_info.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(i32)]
     lib.bpsf_tile_options.argtypes = [vp, P(i32), i32]
     lib.bpsf_reserve.argtypes = [vp, i64, P(bpsf_params)]
+    lib.bpsf_set_trial_table.argtypes = [vp, vp, i64, i64]
     lib.bpsf_mix_reserve.argtypes = [vp, i64, P(bpsf_params)]
     lib.bpsf_set_tile.argtypes = [vp, i32, i32]
     lib.bpsf_autotune.argtypes = [vp, vp, P(C.c_double), i64, P(bpsf_params), i32, vp, P(bpsf_tuning)]
@@ -179,6 +180,20 @@ def bpsf_last_timing(handle) -> dict:
     ms = (C.c_float * 4)()
     _check(LIB.bpsf_last_timing(C.c_void_p(handle), ms))
     return {"total": ms[0], "main": ms[1], "trials": ms[2], "rerun": ms[3]}
+
+
+def bpsf_set_trial_table(handle, masks=None) -> None:
+    """Trial list for TRIALS_TABLE: a device uint32 tensor [n_trials] (every
+    shot) or [shots, n_trials] (one list per shot), kept alive by the caller;
+    None clears it."""
+    if masks is None:
+        _check(LIB.bpsf_set_trial_table(C.c_void_p(handle), None, 0, 0))
+        return
+    if not masks.is_cuda or not masks.is_contiguous():
+        raise ValueError("masks must be a contiguous device tensor")
+    n = int(masks.shape[-1])
+    stride = n if masks.dim() == 2 else 0
+    _check(LIB.bpsf_set_trial_table(C.c_void_p(handle), C.c_void_p(masks.data_ptr()), n, stride))
 
 
 def bpsf_reserve(handle, shots: int, params: bpsf_params) -> None:

@@ -83,6 +83,9 @@ struct bpsf_code_s {
   DevBuf llr32, llr64;
   // trial masks cache
   int masks_k = -1, masks_mode = -1, masks_wmax = -1, n_trials = 0;
+  // the caller's trial list (BPSF_TRIALS_TABLE)
+  const uint32_t* table = nullptr;
+  int64_t table_n = 0, table_stride = 0;
   DevBuf masks;
   // scratch
   DevBuf records, keys, counters;
@@ -171,14 +174,18 @@ int check_params(const bpsf_params* p)
   if (p->k < 0 || p->k > 16) return fail(BPSF_EINVAL, "k must be in 0..16");
   if (p->k > 0 && (p->cand_max_iter < 1 || p->cand_max_iter >= (1 << KEY_ITER_BITS)))
     return fail(BPSF_EINVAL, "cand_max_iter must be in 1..4095");
-  if (p->cand_mode != BPSF_TRIALS_ALL_SUBSETS && p->cand_mode != BPSF_TRIALS_WEIGHT_LE)
+  if (p->cand_mode != BPSF_TRIALS_ALL_SUBSETS && p->cand_mode != BPSF_TRIALS_WEIGHT_LE &&
+      p->cand_mode != BPSF_TRIALS_TABLE)
     return fail(BPSF_EINVAL, "unknown cand_mode");
   if (p->k > 0 && p->cand_mode == BPSF_TRIALS_WEIGHT_LE && (p->w_max < 1 || p->w_max > p->k))
     return fail(BPSF_EINVAL, "w_max must be in 1..k");
   if (p->select_mode != BPSF_SELECT_MIN_WEIGHT && p->select_mode != BPSF_SELECT_FIRST)
     return fail(BPSF_EINVAL, "unknown select_mode");
+  if ((p->flags & BPSF_FLAG_PRUNE) && p->select_mode != BPSF_SELECT_FIRST)
+    return fail(BPSF_EINVAL, "BPSF_FLAG_PRUNE needs BPSF_SELECT_FIRST");
   if (!(p->alpha >= 0.0) || !isfinite(p->alpha)) return fail(BPSF_EINVAL, "alpha must be finite and >= 0");
-  if (p->flags & ~(BPSF_FLAG_NO_EARLY_STOP | BPSF_FLAG_FORCE_PP)) return fail(BPSF_EINVAL, "unknown flags");
+  if (p->flags & ~(BPSF_FLAG_NO_EARLY_STOP | BPSF_FLAG_FORCE_PP | BPSF_FLAG_PRUNE))
+    return fail(BPSF_EINVAL, "unknown flags");
   if (p->precision != BPSF_PREC_FP32 && p->precision != BPSF_PREC_FP64) return fail(BPSF_EINVAL, "unknown precision");
   return 0;
 }
@@ -211,6 +218,10 @@ int update_llr(bpsf_code_s* c, const double* priors)
 
 int update_masks(bpsf_code_s* c, const bpsf_params* p)
 {
+  if (p->cand_mode == BPSF_TRIALS_TABLE) {
+    if (p->k > 0 && !c->table) return fail(BPSF_EINVAL, "BPSF_TRIALS_TABLE without a trial table on the code");
+    return 0;
+  }
   const int wm = p->cand_mode == BPSF_TRIALS_WEIGHT_LE ? p->w_max : 0;
   if (c->masks_k == p->k && c->masks_mode == p->cand_mode && c->masks_wmax == wm) return 0;
   std::vector<uint32_t> m = trial_masks(p->k, p->cand_mode, wm);
@@ -282,11 +293,18 @@ int fill_code_args(const bpsf_code_s* c, const bpsf_params* p, const TileDesc& t
   a.max_iter = p->max_iter;
   a.cand_max_iter = p->k > 0 ? p->cand_max_iter : 1;
   a.k = p->k;
-  a.n_trials = c->n_trials;
   a.select_first = p->select_mode == BPSF_SELECT_FIRST;
   a.flags = p->flags;
   a.alpha = p->alpha;
-  a.trial_masks = static_cast<const uint32_t*>(c->masks.p);
+  if (p->cand_mode == BPSF_TRIALS_TABLE) {
+    a.n_trials = p->k > 0 ? (int)c->table_n : 0;
+    a.trial_masks = c->table;
+    a.mask_stride = c->table_stride;
+  } else {
+    a.n_trials = c->n_trials;
+    a.trial_masks = static_cast<const uint32_t*>(c->masks.p);
+    a.mask_stride = 0;
+  }
   // record: header, s bits per lane, every Phi column's share per lane, Phi
   const int kk = p->k > 0 ? p->k : 1;
   a.rec_stride = REC_HDR + G * (kk + 1) + kk;
@@ -526,6 +544,7 @@ int64_t bpsf_num_trials(const bpsf_params* p, uint32_t* masks_out, int64_t cap)
 {
   int rc = check_params(p);
   if (rc) return rc;
+  if (p->cand_mode == BPSF_TRIALS_TABLE) return fail(BPSF_EINVAL, "a BPSF_TRIALS_TABLE list is the caller's");
   const std::vector<uint32_t> m = trial_masks(p->k, p->cand_mode, p->w_max);
   if (masks_out)
     for (int64_t i = 0; i < (int64_t)m.size() && i < cap; ++i) masks_out[i] = m[(size_t)i];
@@ -921,6 +940,23 @@ int bpsf_mix_reserve(bpsf_mix m, int64_t shots, const bpsf_params* p)
       m->records.ensure(sizeof(int32_t) * n * (size_t)stride) || m->keys.ensure(sizeof(unsigned long long) * n) ||
       m->counters.ensure(sizeof(unsigned long long) * ((size_t)CNT_WORDS * m->n + MIX_WORDS)))
     return fail(BPSF_ENOMEM, "scratch for %lld shots", (long long)shots);
+  return 0;
+}
+
+int bpsf_set_trial_table(bpsf_code c, const uint32_t* masks, int64_t n_trials, int64_t stride)
+{
+  if (!c) return fail(BPSF_EINVAL, "code is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (!masks) {
+    c->table = nullptr;
+    c->table_n = c->table_stride = 0;
+    return 0;
+  }
+  if (n_trials < 1 || n_trials > 0x7fffffffLL) return fail(BPSF_EINVAL, "n_trials must be in 1..2^31-1");
+  if (stride != 0 && stride != n_trials) return fail(BPSF_EINVAL, "stride must be 0 or n_trials");
+  c->table = masks;
+  c->table_n = n_trials;
+  c->table_stride = stride;
   return 0;
 }
 

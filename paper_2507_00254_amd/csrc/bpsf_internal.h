@@ -64,7 +64,8 @@ struct Args {
   // parameters
   int max_iter, cand_max_iter, k, n_trials, select_first, flags;
   double alpha;              // > 0 fixed; 0 adaptive 1 - 2^-i
-  const uint32_t* trial_masks;  // [n_trials]
+  const uint32_t* trial_masks;  // shot i's trial t at [i * mask_stride + t]
+  int64_t mask_stride;          // 0: one list for every shot
   // scratch (device)
   int32_t* records;          // [cap][rec_stride] (shared by the codes of a mixed launch)
   int rec_stride;
@@ -77,7 +78,7 @@ struct Args {
   int chunk;                 // tasks reserved per counter update
 };
 
-enum : int { FLAG_NO_EARLY_STOP = 1, FLAG_FORCE_PP = 2 };
+enum : int { FLAG_NO_EARLY_STOP = 1, FLAG_FORCE_PP = 2, FLAG_PRUNE = 4 };
 
 // Sets the calling thread's message for bpsf_last_error and returns code.
 int report_error(int code, const char* msg);

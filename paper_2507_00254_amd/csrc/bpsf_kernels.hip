@@ -296,9 +296,17 @@ __device__ __forceinline__ void decode_code(const Args& a)
         if (j < a.k) pf_tw[j] = (uint32_t)r[REC_HDR + G + j * G + q];
       pf_shot = r[REC_SHOT];
       pf_miters = r[REC_MAIN_ITERS];
-      pf_mask = a.trial_masks[ti];
+      pf_mask = a.trial_masks[(long long)pf_shot * a.mask_stride + ti];
       pf_ti = (int)ti;
       pf_f = (int)f;   // records never exceed the shots of one call (int32, checked on the host)
+      if constexpr (MODE == MODE_CAND) {
+        // lowest-index selection: a trial after one that already succeeded
+        // cannot be selected; skip it (a stale key only skips less)
+        if (a.flags & FLAG_PRUNE) {
+          const unsigned long long kk = __hip_atomic_load(&a.keys[f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (kk != KEY_NONE && (long long)((kk >> KEY_ITER_BITS) & 0xffffffffull) < ti) pf_f = -1;
+        }
+      }
     }
   };
 
@@ -307,6 +315,7 @@ __device__ __forceinline__ void decode_code(const Args& a)
     if (pend_n == 0) return;
     bool valid = d < pend_n;
     if constexpr (MODE == MODE_EMIT) valid = valid && pf_key != KEY_NONE;
+    if constexpr (MODE == MODE_CAND) valid = valid && pf_f >= 0;   // skipped by pruning
     // compact: rank of my entry among valid entries (count q == 0 lanes below)
     const unsigned long long vb = __ballot(valid && q == 0);
     const int rank = __popcll(vb & ((1ull << (d * G)) - 1ull));
@@ -519,7 +528,17 @@ __device__ __forceinline__ void decode_code(const Args& a)
     if (active) iter += 1;
     const int cap = (MODE == MODE_MAIN) ? a.max_iter : a.cand_max_iter;
     const bool stop_ok = conv && !(a.flags & FLAG_NO_EARLY_STOP);
-    const bool fin = active && (stop_ok || iter >= cap);
+    bool fin = active && (stop_ok || iter >= cap);
+    if constexpr (MODE == MODE_CAND) {
+      // stop a trial once a lower-index trial of its shot has succeeded
+      if ((a.flags & FLAG_PRUNE) && __ballot(active && !fin && (iter & 1) == 0) != 0ull) {
+        unsigned long long kk = KEY_NONE;
+        if (active && q == 0) kk = __hip_atomic_load(&a.keys[rec], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        kk = __shfl(kk, d * G);
+        if (active && (iter & 1) == 0 && kk != KEY_NONE && (int)((kk >> KEY_ITER_BITS) & 0xffffffffull) < trial)
+          fin = true;
+      }
+    }
 
     if (__ballot(fin) != 0ull) {
       // G through an opaque copy: keeps the compiler from hoisting the bit
