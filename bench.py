@@ -206,6 +206,66 @@ def run_mixed(args):
     print(json.dumps(out), flush=True)
 
 
+def run_phen(args):
+    """Phenomenological noise on [[144,12,12]] over 12 rounds (864 x 2592, one
+    decode per workgroup of three waves): 10^5 shots at each of p = q = 0.002
+    and 0.005, 200 first-BP iterations, k = 8 (256 trials of 30 iterations),
+    float messages."""
+    import torch
+
+    from paper_2507_00254_amd import bpsf as B
+    from workloads import codes, shots
+
+    torch.cuda.set_device(0)
+    h = codes.phenomenological(codes.bb144().hx, 12)
+    n = 100_000
+    prm = B.make_params(max_iter=200, cand_max_iter=30, k=8, alpha=0.625, precision=B.PREC_FP32)
+    handle = B.bpsf_load_code(h)
+    edges = B.bpsf_code_info(handle)["edges"]
+    stream = torch.cuda.current_stream()
+    rows = []
+    for p in (0.002, 0.005):
+        _, syn = shots.make_shots(h, p, n, shots.stream_key(shots.MASTER_SEED, 4, h.shape[1], int(round(p * 1e5))))
+        s = torch.from_numpy(syn).cuda()
+        corr = torch.empty((n, h.shape[1]), dtype=torch.uint8, device="cuda")
+        conv = torch.empty((n,), dtype=torch.uint8, device="cuda")
+        it = torch.empty((n,), dtype=torch.int32, device="cuda")
+        pri = np.full(h.shape[1], p)
+        for _ in range(args.warmup):
+            B.bpsf_decode(handle, s, pri, prm, corr, conv, it, stream)
+        torch.cuda.synchronize()
+        B.bpsf_set_timing(handle, True)
+        phase = {"main": 0.0, "trials": 0.0, "rerun": 0.0}
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            B.bpsf_decode(handle, s, pri, prm, corr, conv, it, stream)
+            tm = B.bpsf_last_timing(handle)
+            for k2 in phase:
+                phase[k2] += tm[k2]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        B.bpsf_set_timing(handle, False)
+        st = B.bpsf_last_stats(handle, stream)
+        iters = {"main": st["main_iterations"], "trials": st["trial_iterations"], "rerun": st["rerun_iterations"]}
+        avg = {k2: v / args.steps for k2, v in phase.items()}
+        dom = max(avg, key=avg.get)
+        ach = EDGE_BYTES * edges * iters[dom] / (avg[dom] * 1e-3) / 1e9
+        rows.append({"p": p, "shots": n, "ms_per_step": ms, "value": n / (ms * 1e-3), "phases_ms": avg,
+                     "work": {**iters, "failed_shots": st["failed_shots"], "errors": st["errors"],
+                              "converged_rate": float(conv.float().mean().item())},
+                     "roofline": {"bound": "lds", "kernel": dom, "achieved": ach, "peak": LDS_PEAK_GBS,
+                                  "unit": "GB/s", "frac": ach / LDS_PEAK_GBS,
+                                  "per_unit": f"{EDGE_BYTES} B per edge-iteration x {edges} edges x {iters[dom]} "
+                                              f"iterations"}})
+        print(json.dumps(rows[-1]), flush=True)
+    B.bpsf_free_code(handle)
+    print(json.dumps({"metric": "decoded shots/s, phenomenological [[144,12,12]] over 12 rounds (864 x 2592)",
+                      "unit": "shots/s", "n_gpus": 1, "dtype": "f32",
+                      "data": "synthetic (seeded i.i.d. data and measurement flips, p = q)",
+                      "config": {"workload": "phen144_r12_1e5", "max_iter": 200, "k": 8, "trials": 256,
+                                 "trial_iter": 30, "alpha": 0.625}, "points": rows}), flush=True)
+
+
 def run_serve(args):
     """Open-loop serving of the five-code mix: Poisson arrivals of requests of
     U{1..256} shots of a uniformly drawn code, at each offered load, through
@@ -274,7 +334,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-calls", type=int, default=200)
-    ap.add_argument("--workload", choices=("bb144", "mixed5", "serve"), default="bb144",
+    ap.add_argument("--workload", choices=("bb144", "mixed5", "serve", "phen"), default="bb144",
                     help="bb144: the headline workload; mixed5: five BB codes' shots interleaved in one call; "
                          "serve: open-loop request serving, batched vs per-request, over a load sweep")
     ap.add_argument("--loads", type=str, default="1e4,3e4,1e5,3e5,1e6,3e6,1e7",
@@ -302,6 +362,9 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "phen":
+        run_phen(args)
         return
 
     import torch

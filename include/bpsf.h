@@ -95,7 +95,13 @@ typedef struct {
  * weight 6 and column weight 3 of up to 576 checks and 1152 bits (the
  * bivariate-bicycle and coprime-BB codes of Appendix A), and with row weight
  * 10 and column weight 5 of up to 576 checks and 576 bits (the
- * generalized-bicycle code of Appendix A).
+ * generalized-bicycle code of Appendix A); otherwise, codes whose rows have
+ * weight 2..8 and columns weight at most 3 (irregular weights allowed) of up
+ * to 960 checks and 2688 bits run one decode per workgroup of three waves
+ * (e.g. the phenomenological matrix of [[144,12,12]] over 12 rounds; float
+ * messages, and double where the device gives a workgroup enough LDS, else
+ * bpsf_decode fails with BPSF_ENOTSUP). Such codes do not mix with others
+ * (bpsf_mix_create) and have no per-iteration trace or tunable launch shape.
  */
 int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, int32_t N, bpsf_code* out);
 

@@ -21,7 +21,8 @@ ARCH = os.environ.get("BPSF_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-variable",
           "-Wno-unused-but-set-variable"]
-UNITS = [("bpsf_kernels.hip", ["-fno-honor-nans"]), ("bpsf_api.hip", []), ("bpsf_server.hip", [])]
+UNITS = [("bpsf_kernels.hip", ["-fno-honor-nans"]), ("bpsf_wide.hip", ["-fno-honor-nans"]), ("bpsf_api.hip", []),
+         ("bpsf_server.hip", [])]
 
 
 def sources():

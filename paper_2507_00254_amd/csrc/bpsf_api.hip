@@ -73,9 +73,15 @@ struct DevBuf {
 
 struct bpsf_code_s {
   int device = 0;
-  int M = 0, N = 0, E = 0, W = 0, DV = 0;
+  int M = 0, N = 0, E = 0, W = 0, DV = 0;   // W, DV: table widths (padded for wide codes)
+  int rw_max = 0, cw_max = 0;               // largest row and column weight
   int cus = 0;
+  size_t lds_max = 0;                       // LDS bytes a workgroup may use
   DevBuf var_chk, var_pos, ell_col;
+  // codes too large for one wave, or with irregular weights: a wide family
+  int wide = -1;
+  DevBuf row_w, init32, init64;
+  std::vector<int32_t> ell_host;
   // channel LLR cache
   std::vector<double> priors;
   bool uniform = false;       // every prior equal (the LLR is then a kernel scalar)
@@ -208,6 +214,26 @@ int update_llr(bpsf_code_s* c, const double* priors)
     return fail(BPSF_ENOMEM, "LLR buffers");
   HIP_OK(hipMemcpy(c->llr64.p, l64.data(), sizeof(double) * (size_t)c->N, hipMemcpyHostToDevice));
   HIP_OK(hipMemcpy(c->llr32.p, l32.data(), sizeof(float) * (size_t)c->N, hipMemcpyHostToDevice));
+  if (c->wide >= 0) {
+    // initial v2c of every edge position of every (padded) check: the
+    // channel LLR of the edge's bit, +inf where the row has no edge
+    const WideDesc d = wide_desc(c->wide);
+    const size_t MP = (size_t)64 * d.NW * d.IC, n = (size_t)c->W * MP;
+    std::vector<double> i64(n, HUGE_VAL);
+    std::vector<float> i32(n, HUGE_VALF);
+    for (int r = 0; r < c->M; ++r)
+      for (int j = 0; j < c->W; ++j) {
+        const int v = c->ell_host[(size_t)r * c->W + j];
+        if (v >= 0) {
+          i64[(size_t)j * MP + r] = l64[v];
+          i32[(size_t)j * MP + r] = l32[v];
+        }
+      }
+    if (c->init64.ensure(sizeof(double) * n) || c->init32.ensure(sizeof(float) * n))
+      return fail(BPSF_ENOMEM, "initial message tables");
+    HIP_OK(hipMemcpy(c->init64.p, i64.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c->init32.p, i32.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+  }
   c->priors.assign(priors, priors + c->N);
   c->uniform = true;
   for (int v = 1; v < c->N; ++v)
@@ -267,6 +293,7 @@ int occupancy(bool mixed, const TileDesc& t, bool fp64, bool uniform, int mode, 
 
 struct Plan {
   TileDesc tile;
+  int wide = -1;   // wide family of the code, or -1
   Args args;
   size_t lds;
   int grid[3];
@@ -277,7 +304,7 @@ struct Plan {
 int fill_code_args(const bpsf_code_s* c, const bpsf_params* p, const TileDesc& t, Args* out)
 {
   if (p->k > c->N) return fail(BPSF_EINVAL, "k = %d exceeds the %d bits of the code", p->k, c->N);
-  const int G = 64 / t.D;
+  const int G = c->wide >= 0 ? 64 * wide_desc(c->wide).NW : 64 / t.D;   // lanes of a decode
   Args& a = *out;
   memset(&a, 0, sizeof a);
   a.M = c->M;
@@ -288,6 +315,8 @@ int fill_code_args(const bpsf_code_s* c, const bpsf_params* p, const TileDesc& t
   a.ell_col = static_cast<const int32_t*>(c->ell_col.p);
   a.llr = p->precision == BPSF_PREC_FP64 ? c->llr64.p : c->llr32.p;
   a.llr_uniform = c->llr_uniform;
+  a.row_w = static_cast<const uint8_t*>(c->row_w.p);
+  a.edge_init = p->precision == BPSF_PREC_FP64 ? c->init64.p : c->init32.p;
   a.syn_stride = c->M;
   a.corr_stride = c->N;
   a.max_iter = p->max_iter;
@@ -314,7 +343,9 @@ int fill_code_args(const bpsf_code_s* c, const bpsf_params* p, const TileDesc& t
 
 int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
 {
-  if (pick_tile(c, &pl->tile)) return fail(BPSF_ENOTSUP, "no kernel tile for this code");
+  pl->wide = c->wide;
+  if (c->wide >= 0) pl->tile = TileDesc{-1, 1};
+  else if (pick_tile(c, &pl->tile)) return fail(BPSF_ENOTSUP, "no kernel tile for this code");
   const TileDesc& t = pl->tile;
   Args& a = pl->args;
   int rc = fill_code_args(c, p, t, &a);
@@ -331,6 +362,20 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
   a.keys = static_cast<unsigned long long*>(c->keys.p);
   a.counters = static_cast<unsigned long long*>(c->counters.p);
   const bool fp64 = p->precision == BPSF_PREC_FP64;
+  if (c->wide >= 0) {
+    const WideDesc d = wide_desc(c->wide);
+    pl->lds = wide_layout(fp64 ? 8 : 4, d.W, 64 * d.NW * d.IC, d.NW).total;
+    if (pl->lds > c->lds_max)
+      return fail(BPSF_ENOTSUP, "%s messages of this code need %zu bytes of LDS per workgroup, the device gives %zu",
+                  fp64 ? "double" : "float", pl->lds, c->lds_max);
+    for (int mode = 0; mode < 3; ++mode) {
+      int per_cu = 0;
+      if (wide_dispatch(1, c->wide, fp64, mode, a, pl->lds, 0, nullptr, &per_cu) || per_cu < 1)
+        return fail(BPSF_EDEVICE, "occupancy query failed for mode %d", mode);
+      pl->grid[mode] = per_cu * c->cus;
+    }
+    return 0;
+  }
   pl->lds = tile_lds(c, t, fp64, c->uniform);
   for (int mode = 0; mode < 3; ++mode) {
     int per_cu = 0;
@@ -379,11 +424,11 @@ int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, in
   const int E = row_ptr[M];
   if (E > 0 && !col_idx) return fail(BPSF_EINVAL, "col_idx is NULL");
   std::vector<int> colw((size_t)N, 0);
-  int W = -1;
+  int rmin = 1 << 30, rmax = 0;
   for (int c = 0; c < M; ++c) {
     const int w = row_ptr[c + 1] - row_ptr[c];
-    if (W < 0) W = w;
-    if (w != W) return fail(BPSF_ENOTSUP, "rows of unequal weight are not supported");
+    rmin = std::min(rmin, w);
+    rmax = std::max(rmax, w);
     for (int e = row_ptr[c]; e < row_ptr[c + 1]; ++e) {
       const int v = col_idx[e];
       if (v < 0 || v >= N) return fail(BPSF_EINVAL, "col_idx[%d] = %d out of range", e, v);
@@ -391,27 +436,57 @@ int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, in
       ++colw[v];
     }
   }
-  const int DV = colw[0];
-  for (int v = 0; v < N; ++v)
-    if (colw[v] != DV) return fail(BPSF_ENOTSUP, "columns of unequal weight are not supported");
-  if (M > 65535) return fail(BPSF_ENOTSUP, "too many checks");
+  int cmin = 1 << 30, cmax = 0;
+  for (int v = 0; v < N; ++v) {
+    cmin = std::min(cmin, colw[v]);
+    cmax = std::max(cmax, colw[v]);
+  }
+  if (M >= 65535) return fail(BPSF_ENOTSUP, "too many checks");
+  if (rmin < 2) return fail(BPSF_ENOTSUP, "every check needs at least two bits");
+  if (rmax > 255) return fail(BPSF_ENOTSUP, "rows heavier than 255");
 
   bpsf_code_s* c = new (std::nothrow) bpsf_code_s;
   if (!c) return fail(BPSF_ENOMEM, "handle");
   c->M = M;
   c->N = N;
   c->E = E;
-  c->W = W;
-  c->DV = DV;
-  TileDesc t;
-  if (pick_tile(c, &t)) { delete c; return fail(BPSF_ENOTSUP, "no kernel tile for M=%d N=%d W=%d DV=%d", M, N, W, DV); }
+  c->rw_max = rmax;
+  c->cw_max = cmax;
+  // a one-wave family when the code is regular and fits, else a wide one
+  bool one_wave = false;
+  if (rmin == rmax && cmin == cmax) {
+    c->W = rmax;
+    c->DV = cmax;
+    TileDesc t;
+    one_wave = pick_tile(c, &t) == 0;
+  }
+  if (!one_wave) {
+    for (int f = 0; f < wide_count() && c->wide < 0; ++f) {
+      const WideDesc d = wide_desc(f);
+      const int G = 64 * d.NW;
+      if (rmax <= d.W && cmax <= d.DV && M <= G * d.IC && N <= G * d.IV && (int64_t)N * d.DV <= 65535) {
+        c->wide = f;
+        c->W = d.W;
+        c->DV = d.DV;
+      }
+    }
+    if (c->wide < 0) {
+      delete c;
+      return fail(BPSF_ENOTSUP, "no kernel family for M=%d N=%d row weights %d..%d column weights %d..%d", M, N, rmin,
+                  rmax, cmin, cmax);
+    }
+  }
+  const int W = c->W, DV = c->DV;
 
-  // checks of every bit in ascending order, and the bit's position in each row
-  std::vector<uint16_t> vchk((size_t)N * DV);
-  std::vector<uint8_t> vpos((size_t)N * DV);
+  // checks of every bit in ascending order (0xffff past its weight), the
+  // bit's position in each row, the rows by position (-1 past the weight)
+  std::vector<uint16_t> vchk((size_t)N * DV, 0xffff);
+  std::vector<uint8_t> vpos((size_t)N * DV, 0);
   std::vector<int32_t> ell((size_t)M * W, -1);
+  std::vector<uint8_t> roww((size_t)M);
   std::vector<int> fill((size_t)N, 0);
-  for (int r = 0; r < M; ++r)
+  for (int r = 0; r < M; ++r) {
+    roww[r] = (uint8_t)(row_ptr[r + 1] - row_ptr[r]);
     for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
       const int v = col_idx[e];
       const int j = e - row_ptr[r];
@@ -420,22 +495,26 @@ int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, in
       ++fill[v];
       ell[(size_t)r * W + j] = v;
     }
+  }
   int rc = 0;
   if (hipGetDevice(&c->device) != hipSuccess) rc = fail(BPSF_EDEVICE, "hipGetDevice");
   hipDeviceProp_t prop;
   if (!rc && hipGetDeviceProperties(&prop, c->device) != hipSuccess) rc = fail(BPSF_EDEVICE, "hipGetDeviceProperties");
   if (!rc) {
     c->cus = prop.multiProcessorCount;
+    c->lds_max = prop.sharedMemPerBlock;
     // var_chk padded to whole 32-bit words: the kernels copy it by words
     if (c->var_chk.ensure((vchk.size() * 2 + 3) & ~(size_t)3) || c->var_pos.ensure(vpos.size()) ||
-        c->ell_col.ensure(ell.size() * 4))
+        c->ell_col.ensure(ell.size() * 4) || c->row_w.ensure(roww.size()))
       rc = fail(BPSF_ENOMEM, "code tables");
   }
   if (!rc && (hipMemcpy(c->var_chk.p, vchk.data(), vchk.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
               hipMemcpy(c->var_pos.p, vpos.data(), vpos.size(), hipMemcpyHostToDevice) != hipSuccess ||
-              hipMemcpy(c->ell_col.p, ell.data(), ell.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
+              hipMemcpy(c->ell_col.p, ell.data(), ell.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+              hipMemcpy(c->row_w.p, roww.data(), roww.size(), hipMemcpyHostToDevice) != hipSuccess))
     rc = fail(BPSF_EDEVICE, "uploading code tables");
   if (rc) { delete c; return rc; }
+  if (c->wide >= 0) c->ell_host = std::move(ell);
   *out = c;
   return 0;
 }
@@ -453,8 +532,8 @@ int bpsf_code_info(bpsf_code c, int32_t* M, int32_t* N, int32_t* edges, int32_t*
   if (M) *M = c->M;
   if (N) *N = c->N;
   if (edges) *edges = c->E;
-  if (rw) *rw = c->W;
-  if (cw) *cw = c->DV;
+  if (rw) *rw = c->rw_max;
+  if (cw) *cw = c->cw_max;
   return 0;
 }
 
@@ -483,16 +562,18 @@ int bpsf_decode(bpsf_code c, const uint8_t* syndromes, const double* priors, int
   const bool fp64 = p->precision == BPSF_PREC_FP64;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (reset_counters(a.counters, CNT_WORDS, stream)) return fail(BPSF_EDEVICE, "counter reset launch");
+  auto launch = [&](int mode) {
+    return pl.wide >= 0 ? wide_dispatch(0, pl.wide, fp64, mode, a, pl.lds, pl.grid[mode], stream, nullptr)
+                        : tile_dispatch(0, pl.tile, fp64, c->uniform, mode, false, a, pl.lds, pl.grid[mode], stream,
+                                        nullptr);
+  };
   if (c->timing) HIP_OK(hipEventRecord(c->ev[0], st));
-  if (tile_dispatch(0, pl.tile, fp64, c->uniform, MODE_MAIN, false, a, pl.lds, pl.grid[MODE_MAIN], stream, nullptr))
-    return fail(BPSF_EDEVICE, "first-BP launch failed");
+  if (launch(MODE_MAIN)) return fail(BPSF_EDEVICE, "first-BP launch failed");
   if (c->timing) HIP_OK(hipEventRecord(c->ev[1], st));
   if (p->k > 0) {
-    if (tile_dispatch(0, pl.tile, fp64, c->uniform, MODE_CAND, false, a, pl.lds, pl.grid[MODE_CAND], stream, nullptr))
-      return fail(BPSF_EDEVICE, "trial launch failed");
+    if (launch(MODE_CAND)) return fail(BPSF_EDEVICE, "trial launch failed");
     if (c->timing) HIP_OK(hipEventRecord(c->ev[2], st));
-    if (tile_dispatch(0, pl.tile, fp64, c->uniform, MODE_EMIT, false, a, pl.lds, pl.grid[MODE_EMIT], stream, nullptr))
-      return fail(BPSF_EDEVICE, "re-run launch failed");
+    if (launch(MODE_EMIT)) return fail(BPSF_EDEVICE, "re-run launch failed");
     if (c->timing) HIP_OK(hipEventRecord(c->ev[3], st));
   }
   c->timed_last = c->timing;
@@ -557,6 +638,7 @@ int bpsf_bp_trace(bpsf_code c, const uint8_t* syndrome, const double* priors, co
   if (!c || !syndrome || !hard_out || !iters_out || !conv_out) return fail(BPSF_EINVAL, "NULL argument");
   int rc = check_params(p);
   if (rc) return rc;
+  if (c->wide >= 0) return fail(BPSF_ENOTSUP, "per-iteration traces cover codes of the one-wave families");
   bpsf_params q = *p;
   q.k = 0;
   std::lock_guard<std::mutex> lk(c->mu);
@@ -836,6 +918,7 @@ int bpsf_autotune(bpsf_code c, const uint8_t* syndromes, const double* priors, i
                   const bpsf_params* p, int32_t reps, void* stream, bpsf_tuning* out)
 {
   if (!c || !out) return fail(BPSF_EINVAL, "NULL argument");
+  if (c->wide >= 0) return fail(BPSF_ENOTSUP, "the launch shape of a wide code is fixed");
   if (shots < 1 || !syndromes) return fail(BPSF_EINVAL, "need a sample of at least one shot");
   if (reps < 1) return fail(BPSF_EINVAL, "reps < 1");
   int rc = check_params(p);

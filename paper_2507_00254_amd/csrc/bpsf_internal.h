@@ -45,6 +45,8 @@ struct Args {
   const uint8_t* var_pos;    // [N][DV] position of the bit inside each check's row
   const int32_t* ell_col;    // [M][W] bits of each check, row order (ELL, -1 padded)
   const void* llr;           // [N] channel LLR (float or double)
+  const uint8_t* row_w;      // [M] row weights (wide kernels)
+  const void* edge_init;     // [W][MP] initial v2c per edge position and padded check (wide kernels)
   double llr_uniform;        // the common channel LLR when every prior is equal
   // problem (device)
   const uint8_t* syndromes;  // [shots][syn_stride]; the first M bytes of a row are s

@@ -85,6 +85,60 @@ __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int W, int CI, i
   return L;
 }
 
+// Wide families: one decode per workgroup of NW waves (G = 64 NW lanes),
+// lane g owning checks g*IC + k and bits g + G*k; rows and columns may be
+// irregular, padded to W and DV. For codes too large for one wave.
+template <int NW_, int IC_, int IV_, int W_, int DV_>
+struct WideFamily {
+  static constexpr int NW = NW_, IC = IC_, IV = IV_, W = W_, DV = DV_;
+  static constexpr int G = 64 * NW;    // lanes of a decode
+  static constexpr int MP = G * IC;    // padded checks (message stride per edge position)
+  static constexpr int PL = 8, KMAX = 16;
+  static_assert(IC % 2 == 1, "an odd IC keeps check-phase accesses free of bank conflicts");
+  static_assert(IC <= 16 && IV <= 32 && IV * DV <= 64, "items must fit the 16/32/64-bit masks");
+};
+
+// Compiled wide families (NW, IC, IV, W, DV): up to 960 checks and 2688 bits
+// of row weight <= 8 and column weight <= 3 (the phenomenological
+// [[144,12,12]] matrix over 12 rounds is 864 x 2592).
+#define BPSF_WIDE_LIST(X) \
+  X(3, 5, 14, 8, 3)
+
+struct WideDesc {
+  int NW, IC, IV, W, DV;
+};
+
+struct WideLayout {
+  uint32_t msg, zero, dummy, resid, red, task, flags, total;
+};
+
+// LDS of a wide-family workgroup.
+__host__ __device__ inline WideLayout wide_layout(int real_bytes, int W, int MP, int NW)
+{
+  WideLayout L;
+  uint32_t o = 0;
+  L.msg = o;                                           // W x MP messages
+  o += (uint32_t)real_bytes * (uint32_t)(W * MP);
+  o = lds_align16(o);
+  L.zero = o;                                          // reads of missing edges: 0
+  o += 16u;
+  L.dummy = o;                                         // writes of missing edges, one cell per lane
+  o += 4u * 64u * (uint32_t)NW * (real_bytes == 8 ? 2u : 1u);
+  o = lds_align16(o);
+  L.resid = o;                                         // u = H e, one word per padded check
+  o += 4u * (uint32_t)MP;
+  o = lds_align16(o);
+  L.red = o;                                           // per-wave partial reductions
+  o += 4u * (uint32_t)NW;
+  o = lds_align16(o);
+  L.task = o;                                          // claimed task, record, trial, skip
+  o += 8u * 4u;
+  L.flags = o;                                         // per-wave unsatisfied flags + stop, two iterations
+  o += 4u * 2u * (uint32_t)(NW + 1);
+  L.total = lds_align16(o);
+  return L;
+}
+
 struct Args;
 struct MixArgs;
 struct BucketArgs;
@@ -97,6 +151,10 @@ int tile_dispatch(int what, const TileDesc& t, bool fp64, bool uniform_llr, int 
 int mixed_dispatch(int what, int fam, bool fp64, bool uniform_llr, int mode, const MixArgs& m, size_t lds_bytes,
                    int grid, void* stream, int* out);
 int bucket_launch(const BucketArgs& b, void* stream);
+int wide_count();
+WideDesc wide_desc(int fam);
+int wide_dispatch(int what, int fam, bool fp64, int mode, const Args& a, size_t lds_bytes, int grid, void* stream,
+                  int* out);
 int reset_counters(unsigned long long* c, int n, void* stream);   // zero n words
 
 }  // namespace bpsf

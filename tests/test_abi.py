@@ -82,12 +82,22 @@ def test_load_code_rejects_malformed(B, case):
 
 
 def test_load_code_refuses_untiled_shapes(B):
-    h = np.zeros((3, 6), np.uint8)
-    h[0, :4] = 1
-    h[1, 2:6] = 1
-    h[2, [0, 5]] = 1
+    # irregular, and a column of weight 4: no family takes it (checked before any device call)
+    h = np.zeros((4, 6), np.uint8)
+    h[:, 0] = 1
+    h[0, 1:3] = 1
+    h[1, 2:5] = 1
+    h[2, [4, 5]] = 1
+    h[3, [1, 5]] = 1
     with pytest.raises(B.BpsfError) as ei:
         B.bpsf_load_code(h)
+    assert ei.value.code == B.BPSF_ENOTSUP
+    # a check of weight 1
+    h1 = np.zeros((2, 4), np.uint8)
+    h1[0, 0] = 1
+    h1[1, 1:4] = 1
+    with pytest.raises(B.BpsfError) as ei:
+        B.bpsf_load_code(h1)
     assert ei.value.code == B.BPSF_ENOTSUP
 
 
