@@ -70,6 +70,7 @@ typedef struct {
 
 #define OR_NO_EARLY_STOP 1
 #define OR_FORCE_PP 2
+#define OR_LAYERED 4      /* layered (row-serial) schedule instead of flooding */
 
 /* ---------------------------------------------------------------- graph -- */
 
@@ -77,6 +78,8 @@ typedef struct {
     int M, N, E;
     const int32_t *row_ptr, *col_idx;   /* H by rows: edge e = position in col_idx */
     int32_t *var_ptr, *var_edge;        /* edges of each variable, ascending check */
+    int32_t *order;                     /* checks in layered-schedule order */
+    int n_layers;
 } graph;
 
 static int graph_build(graph *g, int M, int N, const int32_t *row_ptr, const int32_t *col_idx)
@@ -105,6 +108,40 @@ static int graph_build(graph *g, int M, int N, const int32_t *row_ptr, const int
             g->var_edge[g->var_ptr[v] + fill[v]++] = e;
         }
     free(fill);
+
+    /* Layers of the layered schedule: in index order, each check takes the
+     * smallest layer that no earlier check sharing a bit with it has. The
+     * schedule visits the checks by layer, then by index. */
+    int32_t *layer = (int32_t *)malloc(sizeof(int32_t) * (size_t)(M > 0 ? M : 1));
+    g->order = (int32_t *)malloc(sizeof(int32_t) * (size_t)(M > 0 ? M : 1));
+    uint8_t *used = (uint8_t *)calloc((size_t)M + 1, 1);
+    if (!layer || !g->order || !used) {
+        free(layer); free(g->order); free(used); free(g->var_ptr); free(g->var_edge);
+        return -1;
+    }
+    g->n_layers = 0;
+    for (int c = 0; c < M; c++) {
+        memset(used, 0, (size_t)M + 1);
+        for (int e = row_ptr[c]; e < row_ptr[c + 1]; e++) {
+            int v = col_idx[e];
+            for (int a = g->var_ptr[v]; a < g->var_ptr[v + 1]; a++) {
+                int e2 = g->var_edge[a];
+                int c2 = 0;
+                while (row_ptr[c2 + 1] <= e2) c2++;   /* the check holding edge e2 */
+                if (c2 < c) used[layer[c2]] = 1;
+            }
+        }
+        int l = 0;
+        while (used[l]) l++;
+        layer[c] = l;
+        if (l + 1 > g->n_layers) g->n_layers = l + 1;
+    }
+    int n = 0;
+    for (int l = 0; l < g->n_layers; l++)
+        for (int c = 0; c < M; c++)
+            if (layer[c] == l) g->order[n++] = c;
+    free(layer);
+    free(used);
     return 0;
 }
 
@@ -112,6 +149,7 @@ static void graph_free(graph *g)
 {
     free(g->var_ptr);
     free(g->var_edge);
+    free(g->order);
 }
 
 /* ------------------------------------------------------------------- BP -- */
@@ -137,6 +175,55 @@ static real alpha_at(const oracle_params *prm, int iter)
 
 /* One BP run on syndrome s.  Returns the number of iterations executed and
  * sets *converged.  With track != 0 the flip counts are accumulated. */
+/* Step 3 for check c: c2v of its edges from the v2c of its edges. */
+static void check_update(const graph *g, const uint8_t *s, const oracle_params *prm, real alpha, int c, bp_work *w)
+{
+    const int lo = g->row_ptr[c], hi = g->row_ptr[c + 1];
+    if (prm->rule == 1) {
+        /* Sum-product: 2 atanh of the product of tanh(x/2) over the other edges. */
+        for (int e = lo; e < hi; e++) {
+            double prod = 1.0;
+            for (int e2 = lo; e2 < hi; e2++)
+                if (e2 != e) prod *= tanh((double)w->v2c[e2] * 0.5);
+            double val = 2.0 * atanh(prod);
+            w->c2v[e] = (real)(s[c] ? -val : val);
+        }
+        return;
+    }
+    /* Min-sum: the minimum |v2c| over the other edges is the overall
+     * minimum except on the edge holding it, where it is the second one. */
+    real min1 = (real)INFINITY, min2 = (real)INFINITY;
+    int arg = -1;
+    int par = s[c] & 1;
+    for (int e = lo; e < hi; e++) {
+        real a = fabs(w->v2c[e]);
+        if (a < min1) { min2 = min1; min1 = a; arg = e; }
+        else if (a < min2) { min2 = a; }
+        par ^= (w->v2c[e] < 0);
+    }
+    for (int e = lo; e < hi; e++) {
+        real mag = (e == arg) ? min2 : min1;
+        int neg = par ^ (w->v2c[e] < 0);   /* (-1)^s times the others' signs */
+        real val = alpha * mag;
+        w->c2v[e] = neg ? -val : val;
+    }
+}
+
+/* Layered schedule: the checks in layer order, each one reading the current
+ * posteriors of its bits, v2c = posterior - its previous c2v, and writing the
+ * posteriors back as v2c + its new c2v before the next check reads them. */
+static void layered_sweep(const graph *g, const uint8_t *s, const oracle_params *prm, real alpha, bp_work *w)
+{
+    for (int i = 0; i < g->M; i++) {
+        const int c = g->order[i];
+        for (int e = g->row_ptr[c]; e < g->row_ptr[c + 1]; e++)
+            w->v2c[e] = w->lout[g->col_idx[e]] - w->c2v[e];
+        check_update(g, s, prm, alpha, c, w);
+        for (int e = g->row_ptr[c]; e < g->row_ptr[c + 1]; e++)
+            w->lout[g->col_idx[e]] = w->v2c[e] + w->c2v[e];
+    }
+}
+
 static int bp_run(const graph *g, const uint8_t *s, const real *L, const oracle_params *prm,
                   int max_iter, int track, bp_work *w, const bp_trace *tr, int *converged)
 {
@@ -146,8 +233,15 @@ static int bp_run(const graph *g, const uint8_t *s, const real *L, const oracle_
     for (int e = 0; e < E; e++) w->c2v[e] = (real)0;
     for (int v = 0; v < N; v++) { w->prev[v] = 0; if (track) w->flips[v] = 0; }
 
+    const int layered = (prm->flags & OR_LAYERED) != 0;
+    if (layered) for (int v = 0; v < N; v++) w->lout[v] = L[v];
     int it = 0;
     for (it = 1; it <= max_iter; it++) {
+        if (layered) {
+            layered_sweep(g, s, prm, alpha_at(prm, it), w);
+            for (int v = 0; v < N; v++) w->hard[v] = (w->lout[v] > 0) ? 0 : 1;
+            goto decided;
+        }
         /* Step 2, V2C: channel LLR plus the messages of all other checks. */
         for (int v = 0; v < N; v++) {
             for (int a = g->var_ptr[v]; a < g->var_ptr[v + 1]; a++) {
@@ -162,37 +256,7 @@ static int bp_run(const graph *g, const uint8_t *s, const real *L, const oracle_
         }
         /* Step 3, C2V. */
         const real alpha = alpha_at(prm, it);
-        for (int c = 0; c < M; c++) {
-            const int lo = g->row_ptr[c], hi = g->row_ptr[c + 1];
-            if (prm->rule == 1) {
-                /* Sum-product: 2 atanh of the product of tanh(x/2) over the other edges. */
-                for (int e = lo; e < hi; e++) {
-                    double prod = 1.0;
-                    for (int e2 = lo; e2 < hi; e2++)
-                        if (e2 != e) prod *= tanh((double)w->v2c[e2] * 0.5);
-                    double val = 2.0 * atanh(prod);
-                    w->c2v[e] = (real)(s[c] ? -val : val);
-                }
-                continue;
-            }
-            /* Min-sum: the minimum |v2c| over the other edges is the overall
-             * minimum except on the edge holding it, where it is the second one. */
-            real min1 = (real)INFINITY, min2 = (real)INFINITY;
-            int arg = -1;
-            int par = s[c] & 1;
-            for (int e = lo; e < hi; e++) {
-                real a = fabs(w->v2c[e]);
-                if (a < min1) { min2 = min1; min1 = a; arg = e; }
-                else if (a < min2) { min2 = a; }
-                par ^= (w->v2c[e] < 0);
-            }
-            for (int e = lo; e < hi; e++) {
-                real mag = (e == arg) ? min2 : min1;
-                int neg = par ^ (w->v2c[e] < 0);   /* (-1)^s times the others' signs */
-                real val = alpha * mag;
-                w->c2v[e] = neg ? -val : val;
-            }
-        }
+        for (int c = 0; c < M; c++) check_update(g, s, prm, alpha, c, w);
         /* Step 4: marginal LLR and hard decision. */
         for (int v = 0; v < N; v++) {
             real acc = L[v];
@@ -200,6 +264,7 @@ static int bp_run(const graph *g, const uint8_t *s, const real *L, const oracle_
             w->lout[v] = acc;
             w->hard[v] = (acc > 0) ? 0 : 1;
         }
+    decided:
         /* Algorithm 1: oscillation tracking against the previous hard decision. */
         for (int v = 0; v < N; v++) {
             if (track) w->flips[v] += (w->hard[v] ^ w->prev[v]);

@@ -14,7 +14,7 @@ import os
 
 import numpy as np
 
-from oracle.oracle import (ALL_SUBSETS, FIRST, FORCE_PP, MIN_WEIGHT, NO_EARLY_STOP, SUM_PRODUCT,
+from oracle.oracle import (ALL_SUBSETS, FIRST, FORCE_PP, LAYERED, MIN_WEIGHT, NO_EARLY_STOP, SUM_PRODUCT,
                            WEIGHT_LE, Params)
 from workloads import codes, shots
 
@@ -311,6 +311,61 @@ def pin_scale_invariance(O):
         assert np.allclose(2 * x["trace_lout"], y["trace_lout"], rtol=1e-12, atol=1e-12)
 
 
+def pin_layered_tree(O):
+    """The layered schedule has the same fixed point on a tree: min-sum with
+    alpha = 1 run long enough yields the max-marginal LLR."""
+    rng = np.random.default_rng(13)
+    for trial in range(6):
+        h = random_tree(rng, int(rng.integers(5, 12)))
+        m, n = h.shape
+        p = rng.uniform(0.02, 0.4, n)
+        L = llr(p)
+        e = (rng.random(n) < 0.3).astype(np.uint8)
+        s = syndrome(h, e)
+        sol = feasible(h, s)
+        cost = sol @ L
+        want = np.array([cost[sol[:, v] == 1].min() - cost[sol[:, v] == 0].min() for v in range(n)])
+        r = O.bp(h, s, p, Params(alpha=1.0, flags=NO_EARLY_STOP | LAYERED), max_iter=2 * (m + n))
+        assert np.allclose(r["lout"], want, rtol=1e-10, atol=1e-10), (trial, r["lout"], want)
+
+
+def pin_layered_chain(O):
+    """A worked sweep. Checks {0,1}, {1,2}, {2,3}: check 2 shares no bit with
+    check 0, so the layers are {0, 2} then {1}. With every message positive
+    and s = (0, 1, 0), one sweep gives, by hand (a = alpha, L = channel LLRs):
+    checks 0 and 2 add a*L1, a*L0 and a*L3, a*L2 to the posteriors of bits
+    0, 1 and 2, 3; check 1 then reads bits 1 and 2 at L1 + a*L0 and
+    L2 + a*L3 and subtracts a times the other one (its syndrome bit is 1).
+    Flooding, index order or any other order give different numbers."""
+    h = np.array([[1, 1, 0, 0], [0, 1, 1, 0], [0, 0, 1, 1]], np.uint8)
+    p = np.array([0.1, 0.2, 0.25, 0.3])
+    L = llr(p)
+    a = 0.75
+    b1 = L[1] + a * L[0]
+    b2 = L[2] + a * L[3]
+    want = np.array([L[0] + a * L[1], b1 - a * b2, b2 - a * b1, L[3] + a * L[2]])
+    r = O.bp(h, np.array([0, 1, 0], np.uint8), p, Params(alpha=a, flags=NO_EARLY_STOP | LAYERED), max_iter=1)
+    assert np.allclose(r["lout"], want, rtol=1e-12, atol=1e-12), (r["lout"], want)
+
+
+def pin_layered_ml_identity(O):
+    """The ML identity of pin_ml_identity holds with the layered schedule."""
+    rng = np.random.default_rng(17)
+    for h in _small_codes():
+        m, n = h.shape
+        for _ in range(3):
+            e = (rng.random(n) < 0.25).astype(np.uint8)
+            s = syndrome(h, e)
+            sol = feasible(h, s)
+            wmin = sol.sum(axis=1).min()
+            prm = Params(max_iter=8, cand_max_iter=8, k=n, cand_mode=ALL_SUBSETS, select_mode=MIN_WEIGHT,
+                         flags=FORCE_PP | LAYERED)
+            r = O.bpsf_detail(h, s, 0.1, prm)
+            assert r["converged"] == 1 and np.array_equal(syndrome(h, r["correction"]), s)
+            assert int(r["correction"].sum()) == wmin
+
+
 PINS = [pin_tree_min_sum, pin_tree_sum_product, pin_first_iteration_closed_form, pin_zero_syndrome,
         pin_half_prior, pin_ml_identity, pin_converged_invariant, pin_flip_counts, pin_empty_trial,
-        pin_trial_vectors, pin_trial_results, pin_scale_invariance]
+        pin_trial_vectors, pin_trial_results, pin_scale_invariance, pin_layered_tree, pin_layered_chain,
+        pin_layered_ml_identity]

@@ -19,8 +19,8 @@ MUTANTS = [
     ("v2c_drops_channel_llr", "                real acc = L[v];\n                for (int b",
      "                real acc = 0;\n                for (int b"),
     ("v2c_includes_own_edge", "if (e2 != e) acc = acc + w->c2v[e2];", "acc = acc + w->c2v[e2];"),
-    ("c2v_ignores_syndrome", "            int arg = -1;\n            int par = s[c] & 1;",
-     "            int arg = -1;\n            int par = 0;"),
+    ("c2v_ignores_syndrome", "    int arg = -1;\n    int par = s[c] & 1;",
+     "    int arg = -1;\n    int par = 0;"),
     ("c2v_min_includes_own_edge", "real mag = (e == arg) ? min2 : min1;", "real mag = min1;"),
     ("c2v_no_second_min_update", "else if (a < min2) { min2 = a; }", "else { }"),
     ("c2v_no_normalization", "real val = alpha * mag;", "real val = mag;"),
@@ -40,6 +40,11 @@ MUTANTS = [
     ("trial_syndrome_not_flipped", "par ^= t[g->col_idx[e]];", "(void)t;"),
     ("trial_output_not_undone", "for (int v = 0; v < N; v++) w->hard[v] ^= t[v];", "(void)t;"),
     ("selection_keeps_heaviest", "wt < best_w", "wt > best_w"),
+    ("layered_posterior_not_written", "w->lout[g->col_idx[e]] = w->v2c[e] + w->c2v[e];", "(void)0;"),
+    ("layered_no_subtraction", "w->v2c[e] = w->lout[g->col_idx[e]] - w->c2v[e];",
+     "w->v2c[e] = w->lout[g->col_idx[e]];"),
+    ("layered_reverse_order", "const int c = g->order[i];", "const int c = g->order[g->M - 1 - i];"),
+    ("layers_ignore_shared_bits", "if (c2 < c) used[layer[c2]] = 1;", "(void)c2;"),
     ("trial_masks_skip_last", "for (int64_t i = 0; i < n; i++) masks[i] = (uint32_t)i;",
      "for (int64_t i = 0; i < n; i++) masks[i] = (uint32_t)(i ? i - 1 : 0);"),
 ]
