@@ -57,6 +57,15 @@ extern "C" {
 #define BPSF_FLAG_PRUNE 4           /* with BPSF_SELECT_FIRST only: a trial is skipped, or stopped,
                                        once a lower-index trial of its shot has succeeded (the
                                        result is the same; fewer trial iterations run) */
+#define BPSF_FLAG_LAYERED 8         /* layered BP schedule instead of flooding, for every BP of the
+                                       call (Section V runs the [[288,12,18]] circuit-level decoders
+                                       with it, Fig. 288_circ): the checks are
+                                       coloured greedily in index order (each takes the smallest
+                                       layer unused by an earlier check sharing a bit) and visited
+                                       by layer, then index; each check turns the posteriors of its
+                                       bits, less its previous c2v, into v2c, applies Eq. (c2v) and
+                                       adds the new c2v back. Single-code calls on one-wave codes
+                                       only (BPSF_ENOTSUP for wide codes, mixed calls, the server) */
 
 #define BPSF_PREC_FP32 0            /* messages in float */
 #define BPSF_PREC_FP64 1            /* messages in double */

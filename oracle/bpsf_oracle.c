@@ -70,7 +70,7 @@ typedef struct {
 
 #define OR_NO_EARLY_STOP 1
 #define OR_FORCE_PP 2
-#define OR_LAYERED 4      /* layered (row-serial) schedule instead of flooding */
+#define OR_LAYERED 8      /* layered (row-serial) schedule instead of flooding */
 
 /* ---------------------------------------------------------------- graph -- */
 

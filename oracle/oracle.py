@@ -23,7 +23,7 @@ class _Params(C.Structure):
 
 NO_EARLY_STOP = 1
 FORCE_PP = 2
-LAYERED = 4          # layered schedule: checks by greedy layer, then by index
+LAYERED = 8          # layered schedule: checks by greedy layer, then by index
 ALL_SUBSETS, WEIGHT_LE = 0, 1
 MIN_WEIGHT, FIRST = 0, 1
 MIN_SUM, SUM_PRODUCT = 0, 1

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libbpsf.so")
 BPSF_OK, BPSF_EINVAL, BPSF_ENOMEM, BPSF_ENOTSUP, BPSF_EDEVICE = 0, -1, -2, -3, -4
 TRIALS_ALL_SUBSETS, TRIALS_WEIGHT_LE, TRIALS_TABLE = 0, 1, 2
 SELECT_MIN_WEIGHT, SELECT_FIRST = 0, 1
-FLAG_NO_EARLY_STOP, FLAG_FORCE_PP, FLAG_PRUNE = 1, 2, 4
+FLAG_NO_EARLY_STOP, FLAG_FORCE_PP, FLAG_PRUNE, FLAG_LAYERED = 1, 2, 4, 8
 PREC_FP32, PREC_FP64 = 0, 1
 
 

@@ -78,6 +78,10 @@ struct bpsf_code_s {
   int cus = 0;
   size_t lds_max = 0;                       // LDS bytes a workgroup may use
   DevBuf var_chk, var_pos, ell_col;
+  // layered schedule (one-wave codes): layer of every check, bit of every
+  // (check, position), number of layers (0: more than the kernels take)
+  DevBuf check_layer, ell16;
+  int n_layers = 0;
   // codes too large for one wave, or with irregular weights: a wide family
   int wide = -1;
   DevBuf row_w, init32, init64;
@@ -140,10 +144,10 @@ int pick_tile(const bpsf_code_s* c, TileDesc* out)
   return -1;
 }
 
-size_t tile_lds(const bpsf_code_s* c, const TileDesc& t, bool fp64, bool uniform)
+size_t tile_lds(const bpsf_code_s* c, const TileDesc& t, bool fp64, bool uniform, bool layered = false)
 {
   const FamilyDesc f = family_desc(t.fam);
-  return lds_layout(fp64 ? 8 : 4, f.W, 64 * f.IC, c->M, c->N, f.DV, t.D, uniform, 8).total;
+  return lds_layout(fp64 ? 8 : 4, f.W, 64 * f.IC, c->M, c->N, f.DV, t.D, uniform, 8, layered, f.IV).total;
 }
 
 // Trial vectors of Algorithm 1 as k-bit masks over Phi, in trial order.
@@ -190,7 +194,7 @@ int check_params(const bpsf_params* p)
   if ((p->flags & BPSF_FLAG_PRUNE) && p->select_mode != BPSF_SELECT_FIRST)
     return fail(BPSF_EINVAL, "BPSF_FLAG_PRUNE needs BPSF_SELECT_FIRST");
   if (!(p->alpha >= 0.0) || !isfinite(p->alpha)) return fail(BPSF_EINVAL, "alpha must be finite and >= 0");
-  if (p->flags & ~(BPSF_FLAG_NO_EARLY_STOP | BPSF_FLAG_FORCE_PP | BPSF_FLAG_PRUNE))
+  if (p->flags & ~(BPSF_FLAG_NO_EARLY_STOP | BPSF_FLAG_FORCE_PP | BPSF_FLAG_PRUNE | BPSF_FLAG_LAYERED))
     return fail(BPSF_EINVAL, "unknown flags");
   if (p->precision != BPSF_PREC_FP32 && p->precision != BPSF_PREC_FP64) return fail(BPSF_EINVAL, "unknown precision");
   return 0;
@@ -265,14 +269,14 @@ int update_masks(bpsf_code_s* c, const bpsf_params* p)
 // Resident blocks per CU of a kernel at an LDS size (memoized: the answer
 // depends only on the kernel, the LDS bytes and the device).
 int occupancy(bool mixed, const TileDesc& t, bool fp64, bool uniform, int mode, size_t lds, const Args* a,
-              const MixArgs* m, int* out)
+              const MixArgs* m, int* out, bool layered = false)
 {
   static std::mutex mu;
   static std::map<std::tuple<int, int, int, int, int, int, size_t, int>, int> memo;
   int dev = 0;
   (void)hipGetDevice(&dev);
   const auto key = std::make_tuple(dev, (int)mixed, t.fam, mixed ? 0 : t.D, (int)fp64 * 2 + (int)uniform, mode, lds,
-                                   0);
+                                   (int)layered);
   {
     std::lock_guard<std::mutex> lk(mu);
     auto it = memo.find(key);
@@ -283,7 +287,7 @@ int occupancy(bool mixed, const TileDesc& t, bool fp64, bool uniform, int mode, 
   }
   int n = 0;
   const int rc = mixed ? mixed_dispatch(1, t.fam, fp64, uniform, mode, *m, lds, 0, nullptr, &n)
-                       : tile_dispatch(1, t, fp64, uniform, mode, false, *a, lds, 0, nullptr, &n);
+                       : tile_dispatch(1, t, fp64, uniform, mode, false, *a, lds, 0, nullptr, &n, layered);
   if (rc || n < 1) return -1;
   std::lock_guard<std::mutex> lk(mu);
   memo[key] = n;
@@ -317,6 +321,9 @@ int fill_code_args(const bpsf_code_s* c, const bpsf_params* p, const TileDesc& t
   a.llr_uniform = c->llr_uniform;
   a.row_w = static_cast<const uint8_t*>(c->row_w.p);
   a.edge_init = p->precision == BPSF_PREC_FP64 ? c->init64.p : c->init32.p;
+  a.check_layer = static_cast<const uint8_t*>(c->check_layer.p);
+  a.ell16 = static_cast<const uint16_t*>(c->ell16.p);
+  a.n_layers = c->n_layers;
   a.syn_stride = c->M;
   a.corr_stride = c->N;
   a.max_iter = p->max_iter;
@@ -343,6 +350,9 @@ int fill_code_args(const bpsf_code_s* c, const bpsf_params* p, const TileDesc& t
 
 int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
 {
+  const bool layered = (p->flags & BPSF_FLAG_LAYERED) != 0;
+  if (layered && (c->wide >= 0 || c->n_layers < 1))
+    return fail(BPSF_ENOTSUP, "the layered schedule covers codes of the one-wave families with at most 254 layers");
   pl->wide = c->wide;
   if (c->wide >= 0) pl->tile = TileDesc{-1, 1};
   else if (pick_tile(c, &pl->tile)) return fail(BPSF_ENOTSUP, "no kernel tile for this code");
@@ -376,10 +386,13 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
     }
     return 0;
   }
-  pl->lds = tile_lds(c, t, fp64, c->uniform);
+  pl->lds = tile_lds(c, t, fp64, c->uniform, layered);
+  if (pl->lds > c->lds_max)
+    return fail(BPSF_ENOTSUP, "this tile needs %zu bytes of LDS per workgroup, the device gives %zu", pl->lds,
+                c->lds_max);
   for (int mode = 0; mode < 3; ++mode) {
     int per_cu = 0;
-    if (occupancy(false, t, fp64, c->uniform, mode, pl->lds, &a, nullptr, &per_cu))
+    if (occupancy(false, t, fp64, c->uniform, mode, pl->lds, &a, nullptr, &per_cu, layered))
       return fail(BPSF_EDEVICE, "occupancy query failed for mode %d", mode);
     if (c->tuned_wpc > 0 && c->tuned_wpc < per_cu) per_cu = c->tuned_wpc;
     pl->grid[mode] = per_cu * c->cus;
@@ -496,6 +509,32 @@ int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, in
       ell[(size_t)r * W + j] = v;
     }
   }
+  // layered schedule: in index order, every check takes the smallest layer
+  // not held by an earlier check that shares a bit with it (one-wave codes)
+  std::vector<uint8_t> layer;
+  std::vector<uint16_t> ell16;
+  if (c->wide < 0) {
+    layer.assign((size_t)M, 0);
+    std::vector<uint8_t> taken(256, 0);
+    int nl = 0;
+    for (int r = 0; r < M && nl <= 254; ++r) {
+      std::fill(taken.begin(), taken.end(), 0);
+      for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+        const int v = col_idx[e];
+        for (int i = 0; i < DV; ++i) {
+          const int r2 = vchk[(size_t)v * DV + i];
+          if (r2 < r) taken[layer[(size_t)r2]] = 1;
+        }
+      }
+      int l = 0;
+      while (l < 255 && taken[(size_t)l]) ++l;
+      layer[(size_t)r] = (uint8_t)l;
+      nl = std::max(nl, l + 1);
+    }
+    c->n_layers = nl <= 254 ? nl : 0;
+    ell16.resize(ell.size());
+    for (size_t i = 0; i < ell.size(); ++i) ell16[i] = (uint16_t)ell[i];
+  }
   int rc = 0;
   if (hipGetDevice(&c->device) != hipSuccess) rc = fail(BPSF_EDEVICE, "hipGetDevice");
   hipDeviceProp_t prop;
@@ -513,6 +552,13 @@ int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, in
               hipMemcpy(c->ell_col.p, ell.data(), ell.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
               hipMemcpy(c->row_w.p, roww.data(), roww.size(), hipMemcpyHostToDevice) != hipSuccess))
     rc = fail(BPSF_EDEVICE, "uploading code tables");
+  if (!rc && c->wide < 0) {
+    if (c->check_layer.ensure(layer.size()) || c->ell16.ensure(ell16.size() * 2))
+      rc = fail(BPSF_ENOMEM, "layer tables");
+    else if (hipMemcpy(c->check_layer.p, layer.data(), layer.size(), hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(c->ell16.p, ell16.data(), ell16.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
+      rc = fail(BPSF_EDEVICE, "uploading layer tables");
+  }
   if (rc) { delete c; return rc; }
   if (c->wide >= 0) c->ell_host = std::move(ell);
   *out = c;
@@ -565,7 +611,7 @@ int bpsf_decode(bpsf_code c, const uint8_t* syndromes, const double* priors, int
   auto launch = [&](int mode) {
     return pl.wide >= 0 ? wide_dispatch(0, pl.wide, fp64, mode, a, pl.lds, pl.grid[mode], stream, nullptr)
                         : tile_dispatch(0, pl.tile, fp64, c->uniform, mode, false, a, pl.lds, pl.grid[mode], stream,
-                                        nullptr);
+                                        nullptr, (p->flags & BPSF_FLAG_LAYERED) != 0);
   };
   if (c->timing) HIP_OK(hipEventRecord(c->ev[0], st));
   if (launch(MODE_MAIN)) return fail(BPSF_EDEVICE, "first-BP launch failed");
@@ -662,7 +708,8 @@ int bpsf_bp_trace(bpsf_code c, const uint8_t* syndrome, const double* priors, co
   a.trace_lout = dl.p;
   a.trace_c2v = dc.p;
   if (reset_counters(a.counters, CNT_WORDS, nullptr)) return fail(BPSF_EDEVICE, "counter reset launch");
-  if (tile_dispatch(0, pl.tile, q.precision == BPSF_PREC_FP64, c->uniform, MODE_MAIN, true, a, pl.lds, 1, nullptr, nullptr))
+  if (tile_dispatch(0, pl.tile, q.precision == BPSF_PREC_FP64, c->uniform, MODE_MAIN, true, a, pl.lds, 1, nullptr, nullptr,
+                    (q.flags & BPSF_FLAG_LAYERED) != 0))
     return fail(BPSF_EDEVICE, "trace launch failed");
   HIP_OK(hipDeviceSynchronize());
   HIP_OK(hipMemcpy(hard_out, dcorr.p, c->N, hipMemcpyDeviceToHost));
@@ -720,6 +767,7 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
   if (!m) return fail(BPSF_EINVAL, "mix is NULL");
   int rc = check_params(p);
   if (rc) return rc;
+  if (p->flags & BPSF_FLAG_LAYERED) return fail(BPSF_ENOTSUP, "mixed-code calls run the flooding schedule only");
   if (shots < 0) return fail(BPSF_EINVAL, "shots < 0");
   if (shots > 0x7fffffffLL) return fail(BPSF_EINVAL, "at most 2^31-1 shots per call");
   if (!priors) return fail(BPSF_EINVAL, "priors is NULL");

@@ -47,6 +47,9 @@ struct Args {
   const void* llr;           // [N] channel LLR (float or double)
   const uint8_t* row_w;      // [M] row weights (wide kernels)
   const void* edge_init;     // [W][MP] initial v2c per edge position and padded check (wide kernels)
+  const uint8_t* check_layer;   // [M] layer of every check (layered schedule)
+  const uint16_t* ell16;        // [M][W] bit of every (check, position) (layered schedule)
+  int n_layers;
   double llr_uniform;        // the common channel LLR when every prior is equal
   // problem (device)
   const uint8_t* syndromes;  // [shots][syn_stride]; the first M bytes of a row are s
@@ -80,7 +83,7 @@ struct Args {
   int chunk;                 // tasks reserved per counter update
 };
 
-enum : int { FLAG_NO_EARLY_STOP = 1, FLAG_FORCE_PP = 2, FLAG_PRUNE = 4 };
+enum : int { FLAG_NO_EARLY_STOP = 1, FLAG_FORCE_PP = 2, FLAG_PRUNE = 4, FLAG_LAYERED = 8 };
 
 // Sets the calling thread's message for bpsf_last_error and returns code.
 int report_error(int code, const char* msg);

@@ -44,13 +44,16 @@ namespace bpsf {
 
 // One phase (MODE) of one code: the wave takes the code's tasks until none is
 // left and returns once its slots have drained. UL: every bit has the same
-// channel LLR (uniform priors), held in a scalar.
-template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE, bool TRACE>
+// channel LLR (uniform priors), held in a scalar. LAY: layered schedule (the
+// checks layer by layer, each reading and updating the bits' posteriors)
+// instead of flooding.
+template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE, bool TRACE, bool LAY>
 __device__ __forceinline__ void decode_code(const Args& a)
 {
   using F = Family<IC, IV, W, DV>;
   using R = RT<Real>;
   constexpr int PL = F::PL, META = F::META, KMAX = F::KMAX, CI = F::CI;
+  static_assert(!LAY || W % 2 == 0, "the layered tables are copied as 32-bit words");
   // launch geometry (uniform)
   const int D = a.D;
   const int LG = 6 - __builtin_ctz((unsigned)D);   // log2 of the lanes per slot
@@ -59,7 +62,7 @@ __device__ __forceinline__ void decode_code(const Args& a)
   const int RING = 2 * D;                          // prefetched tasks (a power of two)
 
   extern __shared__ __align__(16) unsigned char smem[];
-  const LdsLayout lay = lds_layout(sizeof(Real), W, CI, a.M, a.N, DV, D, UL, META);
+  const LdsLayout lay = lds_layout(sizeof(Real), W, CI, a.M, a.N, DV, D, UL, META, LAY, IV);
   Real* msg = reinterpret_cast<Real*>(smem + lay.msg);
   uint32_t* uw = reinterpret_cast<uint32_t*>(smem + lay.resid);
   uint16_t* chk = reinterpret_cast<uint16_t*>(smem + lay.chk);
@@ -67,6 +70,8 @@ __device__ __forceinline__ void decode_code(const Args& a)
   int32_t* ring_meta = reinterpret_cast<int32_t*>(smem + lay.ring_meta);
   uint32_t* ring_syn = reinterpret_cast<uint32_t*>(smem + lay.ring_syn);
   uint32_t* ring_tb = reinterpret_cast<uint32_t*>(smem + lay.ring_tb);
+  Real* lpost = reinterpret_cast<Real*>(smem + lay.lpost);          // LAY: [slot][G*IV] posteriors
+  uint16_t* ellw = reinterpret_cast<uint16_t*>(smem + lay.ellw);    // LAY: [M][W] bit of each edge
 
   const int lane = threadIdx.x;
   const int d = lane >> LG;          // slot
@@ -89,7 +94,14 @@ __device__ __forceinline__ void decode_code(const Args& a)
     for (int i = lane; i < nw; i += 64) dst[i] = src[i];
   }
   for (int i = lane; i < CI; i += 64) uw[i] = 0u;
-  if constexpr (!UL) {
+  if constexpr (LAY) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.ell16);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(ellw);
+    const int nw = (M * W) >> 1;
+#pragma unroll 4
+    for (int i = lane; i < nw; i += 64) dst[i] = src[i];
+  }
+  if constexpr (!UL && !LAY) {
     // channel LLR of the bit on every edge (check c, position j): the value a
     // fresh decode's v2c takes there
     for (int i = lane; i < W * M; i += 64) {
@@ -127,6 +139,17 @@ __device__ __forceinline__ void decode_code(const Args& a)
   }
   if constexpr (UL) Lv[0] = Lu;
   const int cbase = d * MS + q * IC;   // check items: entry of position 0, item 0 (= IC * lane)
+  // LAY: layer of every check item, one byte each (0xff past M)
+  uint32_t lyw[(IC + 3) / 4];
+#pragma unroll
+  for (int w = 0; w < (IC + 3) / 4; ++w) lyw[w] = 0xffffffffu;
+  if constexpr (LAY) {
+#pragma unroll
+    for (int k = 0; k < IC; ++k) {
+      const int c = q * IC + k;
+      if (c < M) lyw[k >> 2] &= ~((uint32_t)(0xffu - a.check_layer[c]) << (8 * (k & 3)));
+    }
+  }
   __syncthreads();
 
   // ---- slot state (uniform over the G lanes of a slot) --------------------
@@ -302,6 +325,11 @@ __device__ __forceinline__ void decode_code(const Args& a)
 #pragma unroll
       for (int b = 0; b < PL; ++b) cnt[b] = 0;
       synbits = ring_syn[e * G + q];
+      if constexpr (LAY) {
+        // posteriors start at the channel LLR
+#pragma unroll
+        for (int k = 0; k < IV; ++k) lpost[d * (G * IV) + q + G * k] = Lv[UL ? 0 : k];
+      }
       if constexpr (MODE == MODE_MAIN) {
         shot = (long long)(uint32_t)ring_meta[e * META + 0] | ((long long)ring_meta[e * META + 1] << 32);
       } else {
@@ -312,8 +340,8 @@ __device__ __forceinline__ void decode_code(const Args& a)
         main_iters = ring_meta[e * META + 4];
       }
     }
-    // messages of taken slots: v2c = L (c2v = 0 before the first iteration);
-    // the whole wave writes one slot at a time
+    // messages of taken slots: v2c = L (c2v = 0 before the first iteration;
+    // LAY keeps c2v, which starts at 0); the whole wave writes one slot at a time
     unsigned long long tb = __ballot(take && q == 0);
     while (tb) {
       const int ld = __ffsll((long long)tb) - 1;
@@ -322,7 +350,8 @@ __device__ __forceinline__ void decode_code(const Args& a)
       for (int c = lane; c < MS; c += 64) {
 #pragma unroll
         for (int j = 0; j < W; ++j) {
-          if constexpr (UL) msg[j * CI + sbase + c] = Lu;
+          if constexpr (LAY) msg[j * CI + sbase + c] = (Real)0;
+          else if constexpr (UL) msg[j * CI + sbase + c] = Lu;
           else msg[j * CI + sbase + c] = c < M ? lrow[j * M + c] : (Real)0;
         }
       }
@@ -343,79 +372,138 @@ __device__ __forceinline__ void decode_code(const Args& a)
     const bool any_active = __ballot(active) != 0ull;
     if (!any_active && exhausted && pend_n == 0 && tail == head) break;
 
-    // ---- check phase: c2v from v2c, Eq. (c2v) ----
     Real alpha = alpha_fixed;
     if (adaptive) alpha = R::adaptive_alpha(iter + 1);
-    {
-      // loads of item k+1 are issued before the stores of item k
-      Real x[2][W];
+    uint32_t nhb = 0;
+    if constexpr (LAY) {
+      // ---- layered sweep: per layer, every check of the layer reads the
+      // posteriors of its bits less its own last c2v, applies Eq. (c2v) and
+      // adds its new c2v back; checks of one layer share no bit ----
+      Real* lp = lpost + d * (G * IV);
+      for (int L = 0; L < a.n_layers; ++L) {
+        uint32_t lm = 0;
 #pragma unroll
-      for (int j = 0; j < W; ++j) x[0][j] = msg[j * CI + cbase];
+        for (int k = 0; k < IC; ++k) lm |= (((lyw[k >> 2] >> (8 * (k & 3))) & 0xffu) == (uint32_t)L ? 1u : 0u) << k;
+        while (lm) {
+          const int k = __builtin_ctz(lm);
+          lm &= lm - 1u;
+          const int c = q * IC + k;
+          Real x[W];
+          int vb[W];
 #pragma unroll
-      for (int k = 0; k < IC; ++k) {
-        Real (&xc)[W] = x[k & 1];
-        if (k + 1 < IC) {
+          for (int j = 0; j < W; ++j) {
+            vb[j] = ellw[c * W + j];
+            x[j] = lp[vb[j]] - msg[j * CI + cbase + k];
+          }
+          Real m1 = R::minr(R::absr(x[0]), R::absr(x[1]));
+          Real m2 = R::maxr(R::absr(x[0]), R::absr(x[1]));
+          uint32_t P = R::sw(x[0]) ^ R::sw(x[1]);
 #pragma unroll
-          for (int j = 0; j < W; ++j) x[(k + 1) & 1][j] = msg[j * CI + cbase + k + 1];
-        }
-        Real m1 = R::minr(R::absr(xc[0]), R::absr(xc[1]));
-        Real m2 = R::maxr(R::absr(xc[0]), R::absr(xc[1]));
-        uint32_t P = R::sw(xc[0]) ^ R::sw(xc[1]);
+          for (int j = 2; j < W; ++j) {
+            m2 = R::med3(m1, m2, R::absr(x[j]));
+            m1 = R::minr(m1, R::absr(x[j]));
+            P ^= R::sw(x[j]);
+          }
+          P ^= (synbits >> k) << 31;                      // (-1)^{s_c}
+          Real s1 = R::flip(alpha * m1, P), s2 = R::flip(alpha * m2, P);
+          R::opaque(s1);
+          R::opaque(s2);
 #pragma unroll
-        for (int j = 2; j < W; ++j) {
-          m2 = R::med3(m1, m2, R::absr(xc[j]));
-          m1 = R::minr(m1, R::absr(xc[j]));
-          P ^= R::sw(xc[j]);
-        }
-        P ^= synbits << (31 - k);                         // (-1)^{s_c}
-        Real s1 = R::flip(alpha * m1, P), s2 = R::flip(alpha * m2, P);
-        R::opaque(s1);
-        R::opaque(s2);
-#pragma unroll
-        for (int j = 0; j < W; ++j) {
-          // the minimum over the other edges: min2 on the edge holding min1
-          const Real o = R::flip(R::absr(xc[j]) == m1 ? s2 : s1, R::sw(xc[j]));
-          msg[j * CI + cbase + k] = o;
-          if constexpr (TRACE) {
-            const int c = q * IC + k;
-            if (d == 0 && active && c < M)
-              reinterpret_cast<Real*>(a.trace_c2v)[(long long)iter * M * W + c * W + j] = o;
+          for (int j = 0; j < W; ++j) {
+            const Real o = R::flip(R::absr(x[j]) == m1 ? s2 : s1, R::sw(x[j]));
+            msg[j * CI + cbase + k] = o;
+            lp[vb[j]] = x[j] + o;
+            if constexpr (TRACE) {
+              if (d == 0 && active && c < M)
+                reinterpret_cast<Real*>(a.trace_c2v)[(long long)iter * M * W + c * W + j] = o;
+            }
           }
         }
+        __syncthreads();   // the next layer reads these posteriors
       }
-    }
-    __syncthreads();
-    commit_prefetch();
-
-    // ---- bit phase: marginal, hard decision, next v2c ----
-    uint32_t nhb = 0;
-    {
-      // every gather is issued before the first store of this phase
-      Real cv[IV][DV];
-#pragma unroll
-      for (int k = 0; k < IV; ++k)
-#pragma unroll
-        for (int j = 0; j < DV; ++j) cv[k][j] = *reinterpret_cast<const Real*>(smem + off[k][j]);
+      commit_prefetch();
+      // hard decisions from the posteriors of my bits
 #pragma unroll
       for (int k = IV - 1; k >= 0; --k) {
-        // prefix sums in ascending check order starting from the channel LLR
-        Real pre[DV + 1];
-        pre[0] = Lv[UL ? 0 : k];
-#pragma unroll
-        for (int j = 0; j < DV; ++j) pre[j + 1] = pre[j] + cv[k][j];
-        const Real lout = pre[DV];
-#pragma unroll
-        for (int j = 0; j < DV; ++j) {
-          Real acc = pre[j];
-#pragma unroll
-          for (int i = j + 1; i < DV; ++i) acc = acc + cv[k][i];
-          *reinterpret_cast<Real*>(smem + off[k][j]) = acc;   // v2c for the next iteration
-        }
-        // shift the hard decision of item k in (items run from IV-1 down to 0)
+        const Real lout = lp[q + G * k];
         nhb = __builtin_amdgcn_alignbit(nhb, R::nonpos_msb(lout), 31);
         if constexpr (TRACE) {
           const int v = q + G * k;
           if (d == 0 && active && v < N) reinterpret_cast<Real*>(a.trace_lout)[(long long)iter * N + v] = lout;
+        }
+      }
+    } else {
+      // ---- check phase: c2v from v2c, Eq. (c2v) ----
+      {
+        // loads of item k+1 are issued before the stores of item k
+        Real x[2][W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) x[0][j] = msg[j * CI + cbase];
+#pragma unroll
+        for (int k = 0; k < IC; ++k) {
+          Real (&xc)[W] = x[k & 1];
+          if (k + 1 < IC) {
+#pragma unroll
+            for (int j = 0; j < W; ++j) x[(k + 1) & 1][j] = msg[j * CI + cbase + k + 1];
+          }
+          Real m1 = R::minr(R::absr(xc[0]), R::absr(xc[1]));
+          Real m2 = R::maxr(R::absr(xc[0]), R::absr(xc[1]));
+          uint32_t P = R::sw(xc[0]) ^ R::sw(xc[1]);
+#pragma unroll
+          for (int j = 2; j < W; ++j) {
+            m2 = R::med3(m1, m2, R::absr(xc[j]));
+            m1 = R::minr(m1, R::absr(xc[j]));
+            P ^= R::sw(xc[j]);
+          }
+          P ^= synbits << (31 - k);                         // (-1)^{s_c}
+          Real s1 = R::flip(alpha * m1, P), s2 = R::flip(alpha * m2, P);
+          R::opaque(s1);
+          R::opaque(s2);
+#pragma unroll
+          for (int j = 0; j < W; ++j) {
+            // the minimum over the other edges: min2 on the edge holding min1
+            const Real o = R::flip(R::absr(xc[j]) == m1 ? s2 : s1, R::sw(xc[j]));
+            msg[j * CI + cbase + k] = o;
+            if constexpr (TRACE) {
+              const int c = q * IC + k;
+              if (d == 0 && active && c < M)
+                reinterpret_cast<Real*>(a.trace_c2v)[(long long)iter * M * W + c * W + j] = o;
+            }
+          }
+        }
+      }
+      __syncthreads();
+      commit_prefetch();
+
+      // ---- bit phase: marginal, hard decision, next v2c ----
+      {
+        // every gather is issued before the first store of this phase
+        Real cv[IV][DV];
+#pragma unroll
+        for (int k = 0; k < IV; ++k)
+#pragma unroll
+          for (int j = 0; j < DV; ++j) cv[k][j] = *reinterpret_cast<const Real*>(smem + off[k][j]);
+#pragma unroll
+        for (int k = IV - 1; k >= 0; --k) {
+          // prefix sums in ascending check order starting from the channel LLR
+          Real pre[DV + 1];
+          pre[0] = Lv[UL ? 0 : k];
+#pragma unroll
+          for (int j = 0; j < DV; ++j) pre[j + 1] = pre[j] + cv[k][j];
+          const Real lout = pre[DV];
+#pragma unroll
+          for (int j = 0; j < DV; ++j) {
+            Real acc = pre[j];
+#pragma unroll
+            for (int i = j + 1; i < DV; ++i) acc = acc + cv[k][i];
+            *reinterpret_cast<Real*>(smem + off[k][j]) = acc;   // v2c for the next iteration
+          }
+          // shift the hard decision of item k in (items run from IV-1 down to 0)
+          nhb = __builtin_amdgcn_alignbit(nhb, R::nonpos_msb(lout), 31);
+          if constexpr (TRACE) {
+            const int v = q + G * k;
+            if (d == 0 && active && v < N) reinterpret_cast<Real*>(a.trace_lout)[(long long)iter * N + v] = lout;
+          }
         }
       }
     }
@@ -589,10 +677,10 @@ __device__ __forceinline__ void decode_code(const Args& a)
   if (lane == 0) atomicAdd(&a.counters[ST_WAVES], 1ull);
 }
 
-template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE, bool TRACE>
+template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE, bool TRACE, bool LAY>
 __global__ __launch_bounds__(64) void bpsf_kernel(Args a)
 {
-  decode_code<Real, IC, IV, W, DV, UL, MODE, TRACE>(a);
+  decode_code<Real, IC, IV, W, DV, UL, MODE, TRACE, LAY>(a);
 }
 
 // ------------------------------------------------------- mixed launches --
@@ -670,7 +758,7 @@ __global__ __launch_bounds__(64) void bpsf_mixed_kernel(const MixArgs m)
       rem = nt - bcast0ll(t);
     }
     if (rem <= 0) continue;
-    decode_code<Real, IC, IV, W, DV, UL, MODE, false>(m.code[c]);
+    decode_code<Real, IC, IV, W, DV, UL, MODE, false, false>(m.code[c]);
   }
 }
 
@@ -739,24 +827,33 @@ __global__ void bpsf_reset_counters(unsigned long long* c, int n)
 
 // ------------------------------------------------------------ dispatch --
 
-template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE, bool TRACE>
+template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE, bool TRACE, bool LAY>
 static int run_kernel(int what, const Args& a, size_t lds, int grid, hipStream_t st, int* out)
 {
   if (what == 1)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bpsf_kernel<Real, IC, IV, W, DV, UL, MODE, TRACE>, 64,
-                                                        lds) == hipSuccess ? 0 : -1;
-  hipLaunchKernelGGL((bpsf_kernel<Real, IC, IV, W, DV, UL, MODE, TRACE>), dim3(grid), dim3(64), lds, st, a);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bpsf_kernel<Real, IC, IV, W, DV, UL, MODE, TRACE, LAY>,
+                                                        64, lds) == hipSuccess ? 0 : -1;
+  hipLaunchKernelGGL((bpsf_kernel<Real, IC, IV, W, DV, UL, MODE, TRACE, LAY>), dim3(grid), dim3(64), lds, st, a);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <typename Real, int IC, int IV, int W, int DV, bool UL>
-static int run_mode(int what, int mode, bool trace, const Args& a, size_t lds, int grid, hipStream_t st, int* out)
+template <typename Real, int IC, int IV, int W, int DV, bool UL, bool LAY>
+static int run_sched(int what, int mode, bool trace, const Args& a, size_t lds, int grid, hipStream_t st, int* out)
 {
   if (mode == MODE_MAIN)
-    return trace ? run_kernel<Real, IC, IV, W, DV, UL, MODE_MAIN, true>(what, a, lds, grid, st, out)
-                 : run_kernel<Real, IC, IV, W, DV, UL, MODE_MAIN, false>(what, a, lds, grid, st, out);
-  if (mode == MODE_CAND) return run_kernel<Real, IC, IV, W, DV, UL, MODE_CAND, false>(what, a, lds, grid, st, out);
-  return run_kernel<Real, IC, IV, W, DV, UL, MODE_EMIT, false>(what, a, lds, grid, st, out);
+    return trace ? run_kernel<Real, IC, IV, W, DV, UL, MODE_MAIN, true, LAY>(what, a, lds, grid, st, out)
+                 : run_kernel<Real, IC, IV, W, DV, UL, MODE_MAIN, false, LAY>(what, a, lds, grid, st, out);
+  if (mode == MODE_CAND)
+    return run_kernel<Real, IC, IV, W, DV, UL, MODE_CAND, false, LAY>(what, a, lds, grid, st, out);
+  return run_kernel<Real, IC, IV, W, DV, UL, MODE_EMIT, false, LAY>(what, a, lds, grid, st, out);
+}
+
+template <typename Real, int IC, int IV, int W, int DV, bool UL>
+static int run_mode(int what, int mode, bool trace, bool layered, const Args& a, size_t lds, int grid, hipStream_t st,
+                    int* out)
+{
+  return layered ? run_sched<Real, IC, IV, W, DV, UL, true>(what, mode, trace, a, lds, grid, st, out)
+                 : run_sched<Real, IC, IV, W, DV, UL, false>(what, mode, trace, a, lds, grid, st, out);
 }
 
 template <typename Real, int IC, int IV, int W, int DV, bool UL>
@@ -801,16 +898,17 @@ FamilyDesc family_desc(int fam)
 }
 
 int tile_dispatch(int what, const TileDesc& t, bool fp64, bool ul, int mode, bool trace, const Args& a, size_t lds,
-                  int grid, void* stream, int* out)
+                  int grid, void* stream, int* out, bool layered)
 {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   int i = 0;
-#define BPSF_FAMILY_CASE(IC_, IV_, W_, DV_)                                                                 \
-  if (i++ == t.fam) {                                                                                       \
-    if (fp64) return ul ? run_mode<double, IC_, IV_, W_, DV_, true>(what, mode, trace, a, lds, grid, st, out) \
-                        : run_mode<double, IC_, IV_, W_, DV_, false>(what, mode, trace, a, lds, grid, st, out); \
-    return ul ? run_mode<float, IC_, IV_, W_, DV_, true>(what, mode, trace, a, lds, grid, st, out)            \
-              : run_mode<float, IC_, IV_, W_, DV_, false>(what, mode, trace, a, lds, grid, st, out);          \
+#define BPSF_FAMILY_CASE(IC_, IV_, W_, DV_)                                                                    \
+  if (i++ == t.fam) {                                                                                          \
+    if (fp64)                                                                                                  \
+      return ul ? run_mode<double, IC_, IV_, W_, DV_, true>(what, mode, trace, layered, a, lds, grid, st, out)   \
+                : run_mode<double, IC_, IV_, W_, DV_, false>(what, mode, trace, layered, a, lds, grid, st, out); \
+    return ul ? run_mode<float, IC_, IV_, W_, DV_, true>(what, mode, trace, layered, a, lds, grid, st, out)      \
+              : run_mode<float, IC_, IV_, W_, DV_, false>(what, mode, trace, layered, a, lds, grid, st, out);    \
   }
   BPSF_FAMILY_LIST(BPSF_FAMILY_CASE)
 #undef BPSF_FAMILY_CASE

@@ -48,7 +48,7 @@ struct FamilyDesc {
 };
 
 struct LdsLayout {
-  uint32_t msg, resid, chk, lrow, ring_meta, ring_tb, ring_syn, total;
+  uint32_t msg, resid, chk, lrow, ring_meta, ring_tb, ring_syn, lpost, ellw, total;
 };
 
 __host__ __device__ inline uint32_t lds_align16(uint32_t o) { return (o + 15u) & ~15u; }
@@ -58,7 +58,7 @@ __host__ __device__ inline uint32_t lds_align16(uint32_t o) { return (o + 15u) &
 // (the channel LLR of every edge, used to reset messages) only when the
 // priors are not uniform.
 __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int W, int CI, int M, int N, int DV, int D,
-                                                bool uniform, int META)
+                                                bool uniform, int META, bool layered = false, int IV = 0)
 {
   LdsLayout L;
   const int ring = 2 * D;
@@ -81,6 +81,14 @@ __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int W, int CI, i
   o += 4u * (uint32_t)(ring * (64 / D));
   L.ring_syn = o;                                      // syndrome bits of every lane of an entry
   o += 4u * (uint32_t)(ring * (64 / D));
+  o = lds_align16(o);
+  // layered schedule: the posterior of every bit of every slot, and the bit
+  // of every (check, position)
+  L.lpost = o;
+  if (layered) o += (uint32_t)real_bytes * 64u * (uint32_t)IV;
+  o = lds_align16(o);
+  L.ellw = o;
+  if (layered) o += 2u * (uint32_t)(M * W);
   L.total = lds_align16(o);
   return L;
 }
@@ -146,7 +154,7 @@ int family_count();
 FamilyDesc family_desc(int fam);
 // what = 0: launch; what = 1: *out = resident blocks per CU
 int tile_dispatch(int what, const TileDesc& t, bool fp64, bool uniform_llr, int mode, bool trace,
-                  const Args& a, size_t lds_bytes, int grid, void* stream, int* out);
+                  const Args& a, size_t lds_bytes, int grid, void* stream, int* out, bool layered = false);
 // every code of m belongs to family fam
 int mixed_dispatch(int what, int fam, bool fp64, bool uniform_llr, int mode, const MixArgs& m, size_t lds_bytes,
                    int grid, void* stream, int* out);

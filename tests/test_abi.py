@@ -57,7 +57,7 @@ def test_trial_enumeration_matches_oracle(B):
 @pytest.mark.parametrize("bad", [dict(max_iter=0), dict(max_iter=256), dict(k=17), dict(k=-1),
                                  dict(cand_mode=2), dict(cand_mode=1, w_max=0), dict(cand_mode=1, k=3, w_max=4),
                                  dict(select_mode=5), dict(alpha=-1.0), dict(alpha=float("nan")),
-                                 dict(alpha=float("inf")), dict(flags=8), dict(precision=2),
+                                 dict(alpha=float("inf")), dict(flags=16), dict(precision=2),
                                  dict(cand_max_iter=0), dict(cand_max_iter=4096)])
 def test_parameter_validation(B, bad):
     with pytest.raises(B.BpsfError) as ei:
