@@ -266,6 +266,122 @@ def run_phen(args):
                                  "trial_iter": 30, "alpha": 0.625}, "points": rows}), flush=True)
 
 
+def _timed_decodes(B, handle, s, pri, prm, corr, conv, it, stream, steps, warmup, table=None):
+    """Warmup, then `steps` timed decodes with per-phase events; returns
+    (ms per step, mean phase ms, stats of the last call)."""
+    import torch
+    for _ in range(warmup):
+        B.bpsf_decode(handle, s, pri, prm, corr, conv, it, stream)
+    torch.cuda.synchronize()
+    B.bpsf_set_timing(handle, True)
+    phase = {"main": 0.0, "trials": 0.0, "rerun": 0.0}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        B.bpsf_decode(handle, s, pri, prm, corr, conv, it, stream)
+        tm = B.bpsf_last_timing(handle)
+        for k2 in phase:
+            phase[k2] += tm.get(k2, 0.0)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    B.bpsf_set_timing(handle, False)
+    st = B.bpsf_last_stats(handle, stream)
+    return ms, {k2: v / steps for k2, v in phase.items()}, st
+
+
+def run_dem(args):
+    """Circuit-level noise on [[144,12,12]] over d = 12 rounds: the detector
+    error model of the memory circuit of workloads.circuit (936 detectors x
+    8,784 mechanisms), 2x10^4 shots sampled from it at each of p = 0.001,
+    0.002, 0.003; adaptive alpha, 100 first-BP iterations, |Phi| = 16 with
+    n_s = 5 sampled trials per weight 1..6 (30 trials of 100 iterations),
+    first success kept with pruning; float messages (sparse kernel family)."""
+    import torch
+
+    from paper_2507_00254_amd import bpsf as B
+    from workloads import circuit, codes, shots, trials
+
+    torch.cuda.set_device(0)
+    c = codes.bb144()
+    n = args.dem_shots
+    stream = torch.cuda.current_stream()
+    masks = trials.sample_trial_list(16, 6, 5, shots.stream_key(shots.MASTER_SEED, 1500))
+    d_masks = torch.from_numpy(masks.view(np.int32)).cuda()
+    prm = B.make_params(max_iter=100, cand_max_iter=100, k=16, cand_mode=B.TRIALS_TABLE, select_mode=1, alpha=0.0,
+                        flags=B.FLAG_PRUNE, precision=B.PREC_FP32)
+    rows = []
+    for p in (0.001, 0.002, 0.003):
+        dem = circuit.build_dem(c.hx, c.hz, 12, p)
+        err, syn, obs = circuit.sample(dem, n, shots.stream_key(shots.MASTER_SEED, 1501, int(round(p * 1e5))))
+        handle = B.bpsf_load_code(dem.h)
+        edges = B.bpsf_code_info(handle)["edges"]
+        B.bpsf_set_trial_table(handle, d_masks)
+        s = torch.from_numpy(syn).cuda()
+        corr = torch.empty((n, dem.h.shape[1]), dtype=torch.uint8, device="cuda")
+        conv = torch.empty((n,), dtype=torch.uint8, device="cuda")
+        it = torch.empty((n,), dtype=torch.int32, device="cuda")
+        ms, avg, st = _timed_decodes(B, handle, s, dem.priors, prm, corr, conv, it, stream, args.steps, args.warmup)
+        iters = {"main": st["main_iterations"], "trials": st["trial_iterations"], "rerun": st["rerun_iterations"]}
+        dom = max(avg, key=avg.get)
+        ach = EDGE_BYTES * edges * iters[dom] / (avg[dom] * 1e-3) / 1e9
+        res = (corr.cpu().numpy() ^ err).astype(np.int64)
+        fail = ((res @ dem.obs.T.astype(np.int64)) & 1).any(axis=1) | (conv.cpu().numpy() == 0)
+        ler = float(fail.mean())
+        rows.append({"p": p, "shots": n, "mechanisms": int(dem.h.shape[1]), "edges": edges,
+                     "ms_per_step": ms, "value": n / (ms * 1e-3), "phases_ms": avg,
+                     "mean_latency_iterations": float(it.float().mean().item()),
+                     "work": {**iters, "failed_shots": st["failed_shots"], "errors": st["errors"]},
+                     "ler": ler, "ler_per_round": 1.0 - (1.0 - ler) ** (1.0 / 12),
+                     "roofline": {"bound": "lds", "kernel": dom, "achieved": ach, "peak": LDS_PEAK_GBS,
+                                  "unit": "GB/s", "frac": ach / LDS_PEAK_GBS,
+                                  "per_unit": f"{EDGE_BYTES} B per edge-iteration x {edges} edges x {iters[dom]} "
+                                              f"iterations"}})
+        print(json.dumps(rows[-1]), flush=True)
+        B.bpsf_free_code(handle)
+    print(json.dumps({"metric": "decoded shots/s, circuit-level [[144,12,12]] detector error model, d = 12",
+                      "unit": "shots/s", "n_gpus": 1, "dtype": "f32",
+                      "data": "synthetic (mechanisms sampled from a self-built detector error model)",
+                      "config": {"workload": "dem144_d12_2e4", "max_iter": 100, "k": 16, "trials": int(len(masks)),
+                                 "trial_iter": 100, "alpha": "adaptive", "select": "first", "prune": True},
+                      "points": rows}), flush=True)
+
+
+def run_layered(args):
+    """Flooding against layered BP on [[288,12,18]] (the code the paper runs
+    with the layered schedule) and [[144,12,12]], code-capacity p = 0.03,
+    2x10^5 shots, the headline's decoder parameters."""
+    import torch
+
+    from paper_2507_00254_amd import bpsf as B
+    from workloads import codes, shots
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    n = 200_000
+    rows = []
+    for name in ("bb288", "bb144"):
+        code = codes.get_code(name)
+        p = 0.03
+        _, syn = shots.make_shots(code.hx, p, n, shots.stream_key(shots.MASTER_SEED, 7, code.n, 3000))
+        handle = B.bpsf_load_code(code.hx)
+        s = torch.from_numpy(syn).cuda()
+        corr = torch.empty((n, code.n), dtype=torch.uint8, device="cuda")
+        conv = torch.empty((n,), dtype=torch.uint8, device="cuda")
+        it = torch.empty((n,), dtype=torch.int32, device="cuda")
+        for sched, flags in (("flooding", 0), ("layered", B.FLAG_LAYERED)):
+            prm = B.make_params(max_iter=100, cand_max_iter=20, k=6, alpha=0.625, flags=flags,
+                                precision=B.PREC_FP32)
+            ms, avg, st = _timed_decodes(B, handle, s, np.full(code.n, p), prm, corr, conv, it, stream,
+                                         args.steps, args.warmup)
+            rows.append({"code": name, "schedule": sched, "shots": n, "ms_per_step": ms, "value": n / (ms * 1e-3),
+                         "phases_ms": avg, "main_iterations_per_shot": st["main_iterations"] / n,
+                         "failed_shots": st["failed_shots"], "converged_rate": float(conv.float().mean().item())})
+            print(json.dumps(rows[-1]), flush=True)
+        B.bpsf_free_code(handle)
+    print(json.dumps({"metric": "decoded shots/s, flooding vs layered BP-SF, p = 0.03", "unit": "shots/s",
+                      "n_gpus": 1, "dtype": "f32", "data": "synthetic (seeded i.i.d. bit flips)",
+                      "config": {"workload": "layered_bb288_bb144_2e5"}, "points": rows}), flush=True)
+
+
 def run_serve(args):
     """Open-loop serving of the five-code mix: Poisson arrivals of requests of
     U{1..256} shots of a uniformly drawn code, at each offered load, through
@@ -334,9 +450,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-calls", type=int, default=200)
-    ap.add_argument("--workload", choices=("bb144", "mixed5", "serve", "phen"), default="bb144",
+    ap.add_argument("--workload", choices=("bb144", "mixed5", "serve", "phen", "dem", "layered"), default="bb144",
                     help="bb144: the headline workload; mixed5: five BB codes' shots interleaved in one call; "
-                         "serve: open-loop request serving, batched vs per-request, over a load sweep")
+                         "serve: open-loop request serving, batched vs per-request, over a load sweep; "
+                         "phen: phenomenological [[144]] over 12 rounds; dem: circuit-level detector error "
+                         "model of [[144]] over 12 rounds; layered: flooding vs layered BP")
+    ap.add_argument("--dem-shots", type=int, default=20_000, help="dem: shots per error rate")
     ap.add_argument("--loads", type=str, default="1e4,3e4,1e5,3e5,1e6,3e6,1e7",
                     help="serve: offered loads in shots/s")
     ap.add_argument("--lanes", type=int, default=2, help="serve: streams of the batched server")
@@ -365,6 +484,12 @@ def main():
         return
     if args.workload == "phen":
         run_phen(args)
+        return
+    if args.workload == "dem":
+        run_dem(args)
+        return
+    if args.workload == "layered":
+        run_layered(args)
         return
 
     import torch

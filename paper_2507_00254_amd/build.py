@@ -21,8 +21,8 @@ ARCH = os.environ.get("BPSF_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-variable",
           "-Wno-unused-but-set-variable"]
-UNITS = [("bpsf_kernels.hip", ["-fno-honor-nans"]), ("bpsf_wide.hip", ["-fno-honor-nans"]), ("bpsf_api.hip", []),
-         ("bpsf_server.hip", [])]
+UNITS = [("bpsf_kernels.hip", ["-fno-honor-nans"]), ("bpsf_wide.hip", ["-fno-honor-nans"]),
+         ("bpsf_sparse.hip", ["-fno-honor-nans"]), ("bpsf_api.hip", []), ("bpsf_server.hip", [])]
 
 
 def sources():
@@ -30,17 +30,28 @@ def sources():
             if f.endswith((".hip", ".h"))] + [os.path.join(os.path.dirname(HERE), "include", "bpsf.h")]
 
 
+def _wait(proc_cmd) -> None:
+    proc, cmd = proc_cmd
+    if proc.wait() != 0:
+        raise subprocess.CalledProcessError(proc.returncode, cmd)
+
+
 def build(verbose: bool = False) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    objs = []
+    objs, procs = [], []
+    # the units compile in parallel (at most four at a time)
     for src, extra in UNITS:
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
         cmd = ["hipcc", *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        if len(procs) >= 4:
+            _wait(procs.pop(0))
+        procs.append((subprocess.Popen(cmd), cmd))
         objs.append(obj)
+    for pr in procs:
+        _wait(pr)
     tmp = LIB + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

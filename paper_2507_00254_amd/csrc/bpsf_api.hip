@@ -85,6 +85,9 @@ struct bpsf_code_s {
   // codes too large for one wave, or with irregular weights: a wide family
   int wide = -1;
   DevBuf row_w, init32, init64;
+  // large irregular matrices: a sparse family (float messages only)
+  int sparse = -1;
+  DevBuf sp_roff, sp_bits, sp_echk;
   std::vector<int32_t> ell_host;
   // channel LLR cache
   std::vector<double> priors;
@@ -297,7 +300,8 @@ int occupancy(bool mixed, const TileDesc& t, bool fp64, bool uniform, int mode, 
 
 struct Plan {
   TileDesc tile;
-  int wide = -1;   // wide family of the code, or -1
+  int wide = -1;     // wide family of the code, or -1
+  int sparse = -1;   // sparse family of the code, or -1
   Args args;
   size_t lds;
   int grid[3];
@@ -308,7 +312,7 @@ struct Plan {
 int fill_code_args(const bpsf_code_s* c, const bpsf_params* p, const TileDesc& t, Args* out)
 {
   if (p->k > c->N) return fail(BPSF_EINVAL, "k = %d exceeds the %d bits of the code", p->k, c->N);
-  const int G = c->wide >= 0 ? 64 * wide_desc(c->wide).NW : 64 / t.D;   // lanes of a decode
+  const int G = c->wide >= 0 ? 64 * wide_desc(c->wide).NW : 64 / t.D;   // lanes of a decode (one-wave, wide)
   Args& a = *out;
   memset(&a, 0, sizeof a);
   a.M = c->M;
@@ -324,6 +328,10 @@ int fill_code_args(const bpsf_code_s* c, const bpsf_params* p, const TileDesc& t
   a.check_layer = static_cast<const uint8_t*>(c->check_layer.p);
   a.ell16 = static_cast<const uint16_t*>(c->ell16.p);
   a.n_layers = c->n_layers;
+  a.E = c->E;
+  a.sp_roff = static_cast<const uint16_t*>(c->sp_roff.p);
+  a.sp_bits = static_cast<const uint32_t*>(c->sp_bits.p);
+  a.sp_echk = static_cast<const uint16_t*>(c->sp_echk.p);
   a.syn_stride = c->M;
   a.corr_stride = c->N;
   a.max_iter = p->max_iter;
@@ -343,7 +351,8 @@ int fill_code_args(const bpsf_code_s* c, const bpsf_params* p, const TileDesc& t
   }
   // record: header, s bits per lane, every Phi column's share per lane, Phi
   const int kk = p->k > 0 ? p->k : 1;
-  a.rec_stride = REC_HDR + G * (kk + 1) + kk;
+  // (sparse family: header and Phi only)
+  a.rec_stride = c->sparse >= 0 ? REC_HDR + kk : REC_HDR + G * (kk + 1) + kk;
   a.chunk = 2 * t.D;
   return 0;
 }
@@ -351,10 +360,13 @@ int fill_code_args(const bpsf_code_s* c, const bpsf_params* p, const TileDesc& t
 int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
 {
   const bool layered = (p->flags & BPSF_FLAG_LAYERED) != 0;
-  if (layered && (c->wide >= 0 || c->n_layers < 1))
+  if (layered && (c->wide >= 0 || c->sparse >= 0 || c->n_layers < 1))
     return fail(BPSF_ENOTSUP, "the layered schedule covers codes of the one-wave families with at most 254 layers");
+  if (c->sparse >= 0 && p->precision != BPSF_PREC_FP32)
+    return fail(BPSF_ENOTSUP, "codes of the sparse family decode with float messages only");
   pl->wide = c->wide;
-  if (c->wide >= 0) pl->tile = TileDesc{-1, 1};
+  pl->sparse = c->sparse;
+  if (c->wide >= 0 || c->sparse >= 0) pl->tile = TileDesc{-1, 1};
   else if (pick_tile(c, &pl->tile)) return fail(BPSF_ENOTSUP, "no kernel tile for this code");
   const TileDesc& t = pl->tile;
   Args& a = pl->args;
@@ -372,6 +384,20 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
   a.keys = static_cast<unsigned long long*>(c->keys.p);
   a.counters = static_cast<unsigned long long*>(c->counters.p);
   const bool fp64 = p->precision == BPSF_PREC_FP64;
+  if (c->sparse >= 0) {
+    const SparseDesc d = sparse_desc(c->sparse);
+    pl->lds = sparse_layout(c->E, c->M, d.NW, d.DVMAX).total;
+    if (pl->lds > c->lds_max)
+      return fail(BPSF_ENOTSUP, "the %d edges of this code need %zu bytes of LDS per workgroup, the device gives %zu",
+                  c->E, pl->lds, c->lds_max);
+    for (int mode = 0; mode < 3; ++mode) {
+      int per_cu = 0;
+      if (sparse_dispatch(1, c->sparse, mode, a, pl->lds, 0, nullptr, &per_cu) || per_cu < 1)
+        return fail(BPSF_EDEVICE, "occupancy query failed for mode %d", mode);
+      pl->grid[mode] = per_cu * c->cus;
+    }
+    return 0;
+  }
   if (c->wide >= 0) {
     const WideDesc d = wide_desc(c->wide);
     pl->lds = wide_layout(fp64 ? 8 : 4, d.W, 64 * d.NW * d.IC, d.NW).total;
@@ -483,7 +509,16 @@ int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, in
         c->DV = d.DV;
       }
     }
-    if (c->wide < 0) {
+    for (int f = 0; f < sparse_count() && c->wide < 0 && c->sparse < 0; ++f) {
+      const SparseDesc d = sparse_desc(f);
+      const int T = 64 * d.NW;
+      if (rmax <= d.WMAX && cmax <= d.DVMAX && M <= T * d.CPT && N <= T * d.BPT && E + d.DVMAX + 1 <= 65535) {
+        c->sparse = f;
+        c->W = d.WMAX;
+        c->DV = d.DVMAX;
+      }
+    }
+    if (c->wide < 0 && c->sparse < 0) {
       delete c;
       return fail(BPSF_ENOTSUP, "no kernel family for M=%d N=%d row weights %d..%d column weights %d..%d", M, N, rmin,
                   rmax, cmin, cmax);
@@ -513,7 +548,7 @@ int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, in
   // not held by an earlier check that shares a bit with it (one-wave codes)
   std::vector<uint8_t> layer;
   std::vector<uint16_t> ell16;
-  if (c->wide < 0) {
+  if (c->wide < 0 && c->sparse < 0) {
     layer.assign((size_t)M, 0);
     std::vector<uint8_t> taken(256, 0);
     int nl = 0;
@@ -552,7 +587,32 @@ int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, in
               hipMemcpy(c->ell_col.p, ell.data(), ell.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
               hipMemcpy(c->row_w.p, roww.data(), roww.size(), hipMemcpyHostToDevice) != hipSuccess))
     rc = fail(BPSF_EDEVICE, "uploading code tables");
-  if (!rc && c->wide < 0) {
+  if (!rc && c->sparse >= 0) {
+    // edges in column-major order (a column's edges by ascending check); the
+    // row offsets of every check (the +inf cell E + DVMAX past the weight)
+    const SparseDesc d = sparse_desc(c->sparse);
+    std::vector<uint32_t> colptr((size_t)N + 1, 0);
+    for (int v = 0; v < N; ++v) colptr[v + 1] = colptr[v] + (uint32_t)colw[v];
+    std::vector<uint16_t> roff((size_t)M * d.WMAX, (uint16_t)(E + d.DVMAX));
+    std::vector<uint16_t> echk((size_t)(E > 0 ? E : 1), 0);
+    std::vector<uint32_t> bits((size_t)N);
+    std::vector<uint32_t> put(colptr.begin(), colptr.end() - 1);
+    for (int r = 0; r < M; ++r)
+      for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+        const int v = col_idx[e];
+        const uint32_t cell = put[v]++;
+        roff[(size_t)r * d.WMAX + (e - row_ptr[r])] = (uint16_t)cell;
+        echk[cell] = (uint16_t)r;
+      }
+    for (int v = 0; v < N; ++v) bits[v] = colptr[v] | ((uint32_t)colw[v] << 16);
+    if (c->sp_roff.ensure(roff.size() * 2) || c->sp_echk.ensure(echk.size() * 2) || c->sp_bits.ensure(bits.size() * 4))
+      rc = fail(BPSF_ENOMEM, "sparse tables");
+    else if (hipMemcpy(c->sp_roff.p, roff.data(), roff.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(c->sp_echk.p, echk.data(), echk.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(c->sp_bits.p, bits.data(), bits.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+      rc = fail(BPSF_EDEVICE, "uploading sparse tables");
+  }
+  if (!rc && c->wide < 0 && c->sparse < 0) {
     if (c->check_layer.ensure(layer.size()) || c->ell16.ensure(ell16.size() * 2))
       rc = fail(BPSF_ENOMEM, "layer tables");
     else if (hipMemcpy(c->check_layer.p, layer.data(), layer.size(), hipMemcpyHostToDevice) != hipSuccess ||
@@ -609,6 +669,7 @@ int bpsf_decode(bpsf_code c, const uint8_t* syndromes, const double* priors, int
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (reset_counters(a.counters, CNT_WORDS, stream)) return fail(BPSF_EDEVICE, "counter reset launch");
   auto launch = [&](int mode) {
+    if (pl.sparse >= 0) return sparse_dispatch(0, pl.sparse, mode, a, pl.lds, pl.grid[mode], stream, nullptr);
     return pl.wide >= 0 ? wide_dispatch(0, pl.wide, fp64, mode, a, pl.lds, pl.grid[mode], stream, nullptr)
                         : tile_dispatch(0, pl.tile, fp64, c->uniform, mode, false, a, pl.lds, pl.grid[mode], stream,
                                         nullptr, (p->flags & BPSF_FLAG_LAYERED) != 0);
@@ -684,7 +745,8 @@ int bpsf_bp_trace(bpsf_code c, const uint8_t* syndrome, const double* priors, co
   if (!c || !syndrome || !hard_out || !iters_out || !conv_out) return fail(BPSF_EINVAL, "NULL argument");
   int rc = check_params(p);
   if (rc) return rc;
-  if (c->wide >= 0) return fail(BPSF_ENOTSUP, "per-iteration traces cover codes of the one-wave families");
+  if (c->wide >= 0 || c->sparse >= 0)
+    return fail(BPSF_ENOTSUP, "per-iteration traces cover codes of the one-wave families");
   bpsf_params q = *p;
   q.k = 0;
   std::lock_guard<std::mutex> lk(c->mu);
@@ -966,7 +1028,7 @@ int bpsf_autotune(bpsf_code c, const uint8_t* syndromes, const double* priors, i
                   const bpsf_params* p, int32_t reps, void* stream, bpsf_tuning* out)
 {
   if (!c || !out) return fail(BPSF_EINVAL, "NULL argument");
-  if (c->wide >= 0) return fail(BPSF_ENOTSUP, "the launch shape of a wide code is fixed");
+  if (c->wide >= 0 || c->sparse >= 0) return fail(BPSF_ENOTSUP, "the launch shape of a wide or sparse code is fixed");
   if (shots < 1 || !syndromes) return fail(BPSF_EINVAL, "need a sample of at least one shot");
   if (reps < 1) return fail(BPSF_EINVAL, "reps < 1");
   int rc = check_params(p);

@@ -80,4 +80,19 @@ __device__ __forceinline__ uint32_t group_reduce(uint32_t x, int G, Op op)
 struct OpAdd { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a + b; } };
 struct OpMax { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a > b ? a : b; } };
 
+// Workgroup-wide max / sum of a per-lane value over NW waves (every thread
+// returns it); red holds NW words of LDS.
+template <int NW, class Op>
+__device__ __forceinline__ uint32_t wg_reduce(uint32_t x, Op op, uint32_t* red)
+{
+  x = group_reduce(x, 64, op);
+  __syncthreads();   // earlier readers of red are done
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  uint32_t r = red[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) r = op(r, red[w]);
+  return r;
+}
+
 }  // namespace bpsf

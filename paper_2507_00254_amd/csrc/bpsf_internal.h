@@ -50,6 +50,11 @@ struct Args {
   const uint8_t* check_layer;   // [M] layer of every check (layered schedule)
   const uint16_t* ell16;        // [M][W] bit of every (check, position) (layered schedule)
   int n_layers;
+  // sparse family (column-major edge order)
+  int E;                        // edges
+  const uint16_t* sp_roff;      // [M][WMAX] edge of every row position, the +inf cell past the weight
+  const uint32_t* sp_bits;      // [N] first edge of the bit | weight << 16
+  const uint16_t* sp_echk;      // [E] check of every edge
   double llr_uniform;        // the common channel LLR when every prior is equal
   // problem (device)
   const uint8_t* syndromes;  // [shots][syn_stride]; the first M bytes of a row are s

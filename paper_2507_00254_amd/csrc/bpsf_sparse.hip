@@ -1,0 +1,472 @@
+// BP-SF kernels for large irregular matrices (circuit-level detector error
+// models, thousands of columns of weight 2..10 and rows of weight up to
+// ~40): one decode per workgroup, float messages. Same method and arithmetic
+// as bpsf_kernels.hip (paper Section II-B steps 1-4, Eq. (c2v), Algorithm 1),
+// same modes and keys.
+//
+// Layout:
+//   * one message per Tanner edge in LDS, edges in column-major order (the
+//     edges of a bit are contiguous, by ascending check): the bit phase reads
+//     and writes a run of consecutive cells; the check phase gathers its
+//     row's cells through offsets held in registers (two 16-bit offsets per
+//     word), padded positions pointing at one cell that holds +inf (no
+//     minimum, no sign) and skipped on the way back; a row is read twice
+//     (minima and parity, then the outputs) instead of being held in
+//     registers;
+//   * thread g owns the checks g + T i and the bits g + T i (T threads);
+//   * u = H e and s (or s') are bit vectors in LDS; u is toggled when a hard
+//     decision flips;
+//   * a failed first BP leaves a record holding its Phi; a trial rebuilds
+//     s' = s + t H^T from the shot's syndrome and the columns of Phi.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "bpsf_device.h"
+#include "bpsf_internal.h"
+#include "bpsf_tiles.h"
+
+namespace bpsf {
+
+namespace {
+
+template <int NW, int CPT, int WMAX, int BPT, int DVMAX, int MODE>
+__device__ __forceinline__ void decode_sparse(const Args& a)
+{
+  using R = RT<float>;
+  using F = SparseFamily<NW, CPT, WMAX, BPT, DVMAX>;
+  constexpr int T = F::T, PL = F::PL, KMAX = F::KMAX;
+  const int M = a.M, N = a.N, E = a.E;
+  const SparseLayout lay = sparse_layout(E, M, NW, DVMAX);
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* msg = reinterpret_cast<float*>(smem + lay.msg);
+  uint32_t* ub = reinterpret_cast<uint32_t*>(smem + lay.ubits);
+  uint32_t* sb = reinterpret_cast<uint32_t*>(smem + lay.sbits);
+  uint32_t* red = reinterpret_cast<uint32_t*>(smem + lay.red);
+  long long* task = reinterpret_cast<long long*>(smem + lay.task);
+  uint32_t* flags = reinterpret_cast<uint32_t*>(smem + lay.flags);
+
+  const int g = threadIdx.x;
+  const int MW = (M + 31) >> 5;        // words of a check bit vector
+  const float* __restrict__ llr = reinterpret_cast<const float*>(a.llr);
+  const bool adaptive = !(a.alpha > 0.0);
+  const float alpha_fixed = adaptive ? 1.0f : (float)a.alpha;
+
+  // ---- per-thread constants -------------------------------------------------
+  // my checks: their edges as packed 16-bit cell indices, and their weights
+  uint32_t roff[CPT][WMAX / 2];
+  uint32_t rw[CPT];
+#pragma unroll
+  for (int i = 0; i < CPT; ++i) {
+    const int c = g + T * i;
+    const uint32_t pad = (uint32_t)(E + DVMAX) * 0x10001u;
+#pragma unroll
+    for (int j = 0; j < WMAX / 2; ++j) roff[i][j] = pad;
+    rw[i] = 0;
+    if (c < M) {
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(a.sp_roff) + (long long)c * (WMAX / 2);
+#pragma unroll
+      for (int j = 0; j < WMAX / 2; ++j) roff[i][j] = src[j];
+      rw[i] = a.row_w[c];
+    }
+  }
+  // my bits: first edge | weight << 16, channel LLR
+  uint32_t bw[BPT];
+  float Lv[BPT];
+  uint32_t vmask = 0;
+#pragma unroll
+  for (int i = 0; i < BPT; ++i) {
+    const int v = g + T * i;
+    bw[i] = 0;
+    Lv[i] = 0.f;
+    if (v < N) {
+      bw[i] = a.sp_bits[v];
+      Lv[i] = llr[v];
+      vmask |= 1u << i;
+    }
+  }
+  // cells past the last column (read by the bit phase, never used) and the
+  // +inf cell of padded row positions
+  for (int i = g; i <= DVMAX; i += T) msg[E + i] = i == DVMAX ? INFINITY : 0.f;
+
+  // ---- task source ----------------------------------------------------------
+  long long n_tasks;
+  unsigned long long* next_ctr;
+  if constexpr (MODE == MODE_MAIN) {
+    n_tasks = a.shots;
+    next_ctr = &a.counters[CNT_MAIN_NEXT];
+  } else if constexpr (MODE == MODE_CAND) {
+    n_tasks = (long long)__atomic_load_n(&a.counters[CNT_FAILED], __ATOMIC_RELAXED) * a.n_trials;
+    next_ctr = &a.counters[CNT_CAND_NEXT];
+  } else {
+    n_tasks = (long long)__atomic_load_n(&a.counters[CNT_FAILED], __ATOMIC_RELAXED);
+    next_ctr = &a.counters[CNT_EMIT_NEXT];
+  }
+  const int rstride = a.rec_stride;
+  unsigned long long st_iters = 0, st_conv = 0, st_err = 0;
+
+  for (;;) {
+    // ---- claim one task for the workgroup (thread 0 decides for everyone) ----
+    __syncthreads();
+    if (g == 0) {
+      const long long t0 = (long long)atomicAdd(next_ctr, 1ull);
+      long long f = 0, ti = 0;
+      int skip = 0;
+      if (MODE != MODE_MAIN && t0 < n_tasks) {
+        if (MODE == MODE_CAND) {
+          f = t0 / a.n_trials;
+          ti = t0 - f * a.n_trials;
+        } else {
+          f = t0;
+        }
+        const unsigned long long kk = __hip_atomic_load(&a.keys[f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (MODE == MODE_EMIT) {
+          skip = kk == KEY_NONE;   // no trial succeeded: the first BP's output stands
+          ti = skip ? 0 : (long long)((kk >> KEY_ITER_BITS) & 0xffffffffull);
+        } else if (a.flags & FLAG_PRUNE) {
+          skip = kk != KEY_NONE && (long long)((kk >> KEY_ITER_BITS) & 0xffffffffull) < ti;
+        }
+      }
+      task[0] = t0;
+      task[1] = f;
+      task[2] = ti;
+      task[3] = skip;
+    }
+    __syncthreads();
+    const long long t = task[0];
+    if (t >= n_tasks) break;
+    if (task[3]) continue;
+
+    // ---- inputs: s into LDS bits, u = 0 ----
+    long long shot = 0;
+    int rec = 0, trial = 0, main_iters = 0;
+    const int32_t* r = nullptr;
+    if constexpr (MODE == MODE_MAIN) {
+      shot = a.shot_base + t;
+    } else {
+      rec = (int)task[1];
+      trial = (int)task[2];
+      r = a.records + (long long)rec * rstride;
+      shot = r[REC_SHOT];
+      main_iters = r[REC_MAIN_ITERS];
+    }
+    {
+      const uint8_t* s = a.syndromes + shot * a.syn_stride;
+      for (int c0 = 0; c0 < M; c0 += T) {
+        const int c = c0 + g;
+        const unsigned long long b = __ballot(c < M && (s[c < M ? c : 0] & 1u));
+        if ((g & 63) == 0 && c < M) {
+          sb[c >> 5] = (uint32_t)b;
+          if ((c >> 5) + 1 < MW) sb[(c >> 5) + 1] = (uint32_t)(b >> 32);
+        }
+      }
+      for (int i = g; i < MW; i += T) ub[i] = 0u;
+    }
+    uint32_t tbits = 0;
+    if constexpr (MODE != MODE_MAIN) {
+      // s' = s + t H^T: thread j flips the checks of Phi[j] when the trial has it
+      __syncthreads();
+      const uint32_t mask = a.trial_masks[shot * a.mask_stride + trial];
+      if (g < a.k && ((mask >> g) & 1u)) {
+        const int v = r[REC_HDR + g];
+        const uint32_t b = a.sp_bits[v];
+        for (uint32_t e = b & 0xffffu; e < (b & 0xffffu) + (b >> 16); ++e) {
+          const int c = a.sp_echk[e];
+          atomicXor(&sb[c >> 5], 1u << (c & 31));
+        }
+      }
+      for (int j = 0; j < KMAX; ++j) {
+        if (j < a.k && ((mask >> j) & 1u)) {
+          const int v = r[REC_HDR + j];
+          if (v % T == g) tbits |= 1u << (v / T);
+        }
+      }
+    }
+    __syncthreads();
+    uint32_t synbits = 0;
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      const int c = g + T * i;
+      if (c < M) synbits |= ((sb[c >> 5] >> (c & 31)) & 1u) << i;
+    }
+
+    // ---- fresh messages: v2c = channel LLR (c2v = 0) ----
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+      const uint32_t e0 = bw[i] & 0xffffu, w = bw[i] >> 16;
+      for (uint32_t j = 0; j < w; ++j) msg[e0 + j] = Lv[i];
+    }
+    __syncthreads();
+
+    uint32_t hb = 0, prevt = 0, prevc = 0;
+    uint32_t cnt[PL];
+#pragma unroll
+    for (int b = 0; b < PL; ++b) cnt[b] = 0;
+    int iter = 0;
+    bool conv = false;
+    const int cap = MODE == MODE_MAIN ? a.max_iter : a.cand_max_iter;
+    for (;;) {
+      // ---- check phase: c2v from v2c, Eq. (c2v) ----
+      const float alpha = adaptive ? R::adaptive_alpha(iter + 1) : alpha_fixed;
+      // the offsets pass through an empty asm every iteration: the compiler
+      // would otherwise hoist every address derived from them out of the
+      // loop and hold it in a register for the whole decode
+#pragma unroll
+      for (int i = 0; i < CPT; ++i)
+#pragma unroll
+        for (int j = 0; j < WMAX / 2; ++j) asm volatile("" : "+v"(roff[i][j]));
+#pragma unroll
+      for (int i = 0; i < BPT; ++i) asm volatile("" : "+v"(bw[i]));
+#pragma unroll
+      for (int i = 0; i < CPT; ++i) {
+        // two passes over the row: minima and sign parity, then the outputs
+        // (the row is read twice rather than held in registers)
+        float m1 = INFINITY, m2 = INFINITY;
+        uint32_t P = synbits << (31 - i);                  // (-1)^{s_c}
+#pragma unroll
+        for (int j = 0; j < WMAX; ++j) {
+          const uint32_t cell = (j & 1) ? (roff[i][j >> 1] >> 16) : (roff[i][j >> 1] & 0xffffu);
+          const float x = msg[cell];
+          m2 = R::med3(m1, m2, R::absr(x));
+          m1 = R::minr(m1, R::absr(x));
+          P ^= R::sw(x);
+        }
+        float s1 = R::flip(alpha * m1, P), s2 = R::flip(alpha * m2, P);
+        R::opaque(s1);
+        R::opaque(s2);
+#pragma unroll
+        for (int j = 0; j < WMAX; ++j) {
+          if ((uint32_t)j < rw[i]) {
+            const uint32_t cell = (j & 1) ? (roff[i][j >> 1] >> 16) : (roff[i][j >> 1] & 0xffffu);
+            const float x = msg[cell];
+            msg[cell] = R::flip(R::absr(x) == m1 ? s2 : s1, R::sw(x));
+          }
+        }
+      }
+      __syncthreads();
+
+      // ---- bit phase: marginal, hard decision, next v2c (ascending checks) ----
+      uint32_t nhb = 0;
+#pragma unroll
+      for (int i = 0; i < BPT; ++i) {
+        const uint32_t e0 = bw[i] & 0xffffu, w = bw[i] >> 16;
+        float cv[DVMAX];
+#pragma unroll
+        for (int j = 0; j < DVMAX; ++j) {
+          const float y = msg[e0 + j];
+          cv[j] = (uint32_t)j < w ? y : 0.f;   // +0 past the weight changes no sum
+        }
+        float pre[DVMAX + 1];
+        pre[0] = Lv[i];
+#pragma unroll
+        for (int j = 0; j < DVMAX; ++j) pre[j + 1] = pre[j] + cv[j];
+#pragma unroll
+        for (int j = 0; j < DVMAX; ++j) {
+          if ((uint32_t)j < w) {
+            float acc = pre[j];
+#pragma unroll
+            for (int q = j + 1; q < DVMAX; ++q) acc = acc + cv[q];
+            msg[e0 + j] = acc;
+          }
+        }
+        nhb |= (R::nonpos_msb(pre[DVMAX]) >> 31) << i;
+      }
+      hb = nhb & vmask;
+      if constexpr (MODE == MODE_MAIN) {
+        const uint32_t fc = hb ^ prevc;
+        prevc = hb;
+        uint32_t carry = fc;
+#pragma unroll
+        for (int b = 0; b < PL; ++b) {
+          const uint32_t tt = cnt[b] & carry;
+          cnt[b] ^= carry;
+          carry = tt;
+        }
+      }
+      {
+        // u follows the hard decisions: toggle the checks of every flipped bit
+        const uint32_t fl = hb ^ prevt;
+        prevt = hb;
+        if (fl) {
+#pragma unroll
+          for (int i = 0; i < BPT; ++i) {
+            if ((fl >> i) & 1u) {
+              const uint32_t e0 = bw[i] & 0xffffu, w = bw[i] >> 16;
+              for (uint32_t e = e0; e < e0 + w; ++e) {
+                const int c = a.sp_echk[e];
+                atomicXor(&ub[c >> 5], 1u << (c & 31));
+              }
+            }
+          }
+        }
+      }
+      __syncthreads();
+
+      // ---- syndrome test over the whole decode ----
+      const uint32_t un = g < MW ? (ub[g] ^ sb[g]) : 0u;
+      const unsigned long long anyw = __ballot(un != 0u);
+      if ((g & 63) == 0) flags[(iter & 1) * (NW + 1) + (g >> 6)] = anyw != 0ull ? 1u : 0u;
+      if constexpr (MODE == MODE_CAND) {
+        if (g == 0) {
+          uint32_t stop = 0;
+          if ((a.flags & FLAG_PRUNE) && (iter & 1) == 1) {
+            const unsigned long long kk = __hip_atomic_load(&a.keys[rec], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            stop = kk != KEY_NONE && (int)((kk >> KEY_ITER_BITS) & 0xffffffffull) < trial;
+          }
+          flags[(iter & 1) * (NW + 1) + NW] = stop;
+        }
+      }
+      __syncthreads();
+      uint32_t anyun = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) anyun |= flags[(iter & 1) * (NW + 1) + w];
+      conv = anyun == 0u;
+      bool stop = false;
+      if constexpr (MODE == MODE_CAND) stop = flags[(iter & 1) * (NW + 1) + NW] != 0u;
+      ++iter;
+      if ((conv && !(a.flags & FLAG_NO_EARLY_STOP)) || iter >= cap || stop) break;
+    }
+
+    // ---- finish ----
+    if constexpr (MODE == MODE_MAIN) {
+      uint8_t* out = a.corrections + shot * a.corr_stride;
+#pragma unroll
+      for (int i = 0; i < BPT; ++i)
+        if ((vmask >> i) & 1u) out[g + T * i] = (uint8_t)((hb >> i) & 1u);
+      if (g == 0) {
+        a.converged[shot] = (uint8_t)conv;
+        a.iterations[shot] = iter;
+        st_iters += (unsigned long long)iter;
+      }
+      if (a.k > 0 && (!conv || (a.flags & FLAG_FORCE_PP))) {
+        // key = count << 16 | (0xffff - v): largest count, then lowest index
+        uint32_t key[BPT];
+#pragma unroll
+        for (int i = 0; i < BPT; ++i) {
+          uint32_t cn = 0;
+#pragma unroll
+          for (int b = 0; b < PL; ++b) cn |= ((cnt[b] >> i) & 1u) << b;
+          key[i] = ((vmask >> i) & 1u) ? ((cn << 16) | (uint32_t)(0xffff - (g + T * i))) : 0u;
+        }
+        if (g == 0) task[1] = (long long)atomicAdd(&a.counters[CNT_FAILED], 1ull);
+        __syncthreads();
+        const int f = (int)task[1];
+        int32_t* rr = a.records + (long long)f * rstride;
+        if (g == 0) {
+          rr[REC_SHOT] = (int32_t)shot;
+          rr[REC_MAIN_ITERS] = iter;
+          rr[REC_MAIN_CONV] = conv ? 1 : 0;
+          a.keys[f] = KEY_NONE;
+        }
+        for (int j = 0; j < a.k; ++j) {
+          uint32_t best = 0;
+#pragma unroll
+          for (int i = 0; i < BPT; ++i) best = key[i] > best ? key[i] : best;
+          best = wg_reduce<NW>(best, OpMax(), red);
+          const int v = best ? 0xffff - (int)(best & 0xffffu) : 0;
+          if (g == 0) rr[REC_HDR + j] = v;
+          if (v % T == g) {
+#pragma unroll
+            for (int i = 0; i < BPT; ++i)
+              if (g + T * i == v) key[i] = 0u;
+          }
+        }
+      }
+    } else if constexpr (MODE == MODE_CAND) {
+      const uint32_t w = wg_reduce<NW>((uint32_t)__popc((hb ^ tbits) & vmask), OpAdd(), red);
+      if (g == 0) {
+        st_iters += (unsigned long long)iter;
+        if (conv) {
+          st_conv += 1;
+          const unsigned long long kw = a.select_first ? 0ull : (unsigned long long)w;
+          const unsigned long long key = (kw << KEY_WEIGHT_SHIFT) |
+                                         ((unsigned long long)(uint32_t)trial << KEY_ITER_BITS) |
+                                         (unsigned long long)iter;
+          atomicMin(&a.keys[rec], key);
+        }
+      }
+    } else {
+      uint8_t* out = a.corrections + shot * a.corr_stride;
+      const uint32_t e = hb ^ tbits;
+#pragma unroll
+      for (int i = 0; i < BPT; ++i)
+        if ((vmask >> i) & 1u) out[g + T * i] = (uint8_t)((e >> i) & 1u);
+      if (g == 0) {
+        a.converged[shot] = 1;
+        a.iterations[shot] = main_iters + iter;
+        st_iters += (unsigned long long)iter;
+        if (!conv) st_err += 1;
+      }
+    }
+  }
+
+  if (g == 0) {
+    const int sidx = MODE == MODE_MAIN ? ST_MAIN_ITERS : (MODE == MODE_CAND ? ST_CAND_ITERS : ST_EMIT_ITERS);
+    if (st_iters) atomicAdd(&a.counters[sidx], st_iters);
+    if (st_conv) atomicAdd(&a.counters[ST_CAND_CONV], st_conv);
+    if (st_err) atomicAdd(&a.counters[ST_ERRORS], st_err);
+    atomicAdd(&a.counters[ST_WAVES], 1ull);
+  }
+}
+
+template <int NW, int CPT, int WMAX, int BPT, int DVMAX, int MODE>
+__global__ __launch_bounds__(64 * NW) void bpsf_sparse_kernel(Args a)
+{
+  decode_sparse<NW, CPT, WMAX, BPT, DVMAX, MODE>(a);
+}
+
+template <int NW, int CPT, int WMAX, int BPT, int DVMAX, int MODE>
+int run_sparse_mode(int what, const Args& a, size_t lds, int grid, hipStream_t st, int* out)
+{
+  // a workgroup may use more than 64 KiB of LDS once the kernel allows it
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(bpsf_sparse_kernel<NW, CPT, WMAX, BPT, DVMAX, MODE>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return -1;
+  if (what == 1)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bpsf_sparse_kernel<NW, CPT, WMAX, BPT, DVMAX, MODE>,
+                                                        64 * NW, lds) == hipSuccess ? 0 : -1;
+  hipLaunchKernelGGL((bpsf_sparse_kernel<NW, CPT, WMAX, BPT, DVMAX, MODE>), dim3(grid), dim3(64 * NW), lds, st, a);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int NW, int CPT, int WMAX, int BPT, int DVMAX>
+int run_sparse(int what, int mode, const Args& a, size_t lds, int grid, hipStream_t st, int* out)
+{
+  if (mode == MODE_MAIN) return run_sparse_mode<NW, CPT, WMAX, BPT, DVMAX, MODE_MAIN>(what, a, lds, grid, st, out);
+  if (mode == MODE_CAND) return run_sparse_mode<NW, CPT, WMAX, BPT, DVMAX, MODE_CAND>(what, a, lds, grid, st, out);
+  return run_sparse_mode<NW, CPT, WMAX, BPT, DVMAX, MODE_EMIT>(what, a, lds, grid, st, out);
+}
+
+}  // namespace
+
+int sparse_count()
+{
+  int n = 0;
+#define BPSF_SPARSE_COUNT(NW_, CPT_, WMAX_, BPT_, DVMAX_) ++n;
+  BPSF_SPARSE_LIST(BPSF_SPARSE_COUNT)
+#undef BPSF_SPARSE_COUNT
+  return n;
+}
+
+SparseDesc sparse_desc(int fam)
+{
+  int i = 0;
+#define BPSF_SPARSE_DESC(NW_, CPT_, WMAX_, BPT_, DVMAX_) \
+  if (i++ == fam) return SparseDesc{NW_, CPT_, WMAX_, BPT_, DVMAX_};
+  BPSF_SPARSE_LIST(BPSF_SPARSE_DESC)
+#undef BPSF_SPARSE_DESC
+  return SparseDesc{0, 0, 0, 0, 0};
+}
+
+int sparse_dispatch(int what, int fam, int mode, const Args& a, size_t lds, int grid, void* stream, int* out)
+{
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int i = 0;
+#define BPSF_SPARSE_CASE(NW_, CPT_, WMAX_, BPT_, DVMAX_) \
+  if (i++ == fam) return run_sparse<NW_, CPT_, WMAX_, BPT_, DVMAX_>(what, mode, a, lds, grid, st, out);
+  BPSF_SPARSE_LIST(BPSF_SPARSE_CASE)
+#undef BPSF_SPARSE_CASE
+  return -2;
+}
+
+}  // namespace bpsf

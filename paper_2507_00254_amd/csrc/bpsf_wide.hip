@@ -28,20 +28,6 @@ namespace bpsf {
 
 namespace {
 
-// Workgroup-wide max / sum of a per-lane value (every thread returns it).
-template <int NW, class Op>
-__device__ __forceinline__ uint32_t wg_reduce(uint32_t x, Op op, uint32_t* red)
-{
-  x = group_reduce(x, 64, op);
-  __syncthreads();   // earlier readers of red are done
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
-  __syncthreads();
-  uint32_t r = red[0];
-#pragma unroll
-  for (int w = 1; w < NW; ++w) r = op(r, red[w]);
-  return r;
-}
-
 template <typename Real, int NW, int IC, int IV, int W, int DV, int MODE>
 __device__ __forceinline__ void decode_wide(const Args& a)
 {

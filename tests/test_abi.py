@@ -82,13 +82,11 @@ def test_load_code_rejects_malformed(B, case):
 
 
 def test_load_code_refuses_untiled_shapes(B):
-    # irregular, and a column of weight 4: no family takes it (checked before any device call)
-    h = np.zeros((4, 6), np.uint8)
+    # irregular, and a column of weight 12: no family takes it (checked before any device call)
+    h = np.zeros((12, 13), np.uint8)
     h[:, 0] = 1
-    h[0, 1:3] = 1
-    h[1, 2:5] = 1
-    h[2, [4, 5]] = 1
-    h[3, [1, 5]] = 1
+    for i in range(12):
+        h[i, 1 + i] = 1
     with pytest.raises(B.BpsfError) as ei:
         B.bpsf_load_code(h)
     assert ei.value.code == B.BPSF_ENOTSUP
