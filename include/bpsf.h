@@ -65,7 +65,8 @@ extern "C" {
                                        by layer, then index; each check turns the posteriors of its
                                        bits, less its previous c2v, into v2c, applies Eq. (c2v) and
                                        adds the new c2v back. Single-code calls on one-wave codes
-                                       only (BPSF_ENOTSUP for wide codes, mixed calls, the server) */
+                                       only (BPSF_ENOTSUP for the irregular-code families, mixed
+                                       calls, the server) */
 
 #define BPSF_PREC_FP32 0            /* messages in float */
 #define BPSF_PREC_FP64 1            /* messages in double */
@@ -109,8 +110,14 @@ typedef struct {
  * to 960 checks and 2688 bits run one decode per workgroup of three waves
  * (e.g. the phenomenological matrix of [[144,12,12]] over 12 rounds; float
  * messages, and double where the device gives a workgroup enough LDS, else
- * bpsf_decode fails with BPSF_ENOTSUP). Such codes do not mix with others
- * (bpsf_mix_create) and have no per-iteration trace or tunable launch shape.
+ * bpsf_decode fails with BPSF_ENOTSUP); otherwise, codes with rows of weight
+ * 2..48 and columns of weight at most 10 of up to 1024 checks and 9216 bits
+ * whose edges fit one workgroup's LDS as floats (4 B per edge: about 39,000
+ * edges) run one decode per workgroup of sixteen waves (e.g. the circuit-level
+ * detector error model of [[144,12,12]] over 12 rounds, Section V-B; float
+ * messages only, double fails with BPSF_ENOTSUP). Codes of these two last
+ * kinds do not mix with others (bpsf_mix_create), take only the flooding
+ * schedule, and have no per-iteration trace or tunable launch shape.
  */
 int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, int32_t N, bpsf_code* out);
 

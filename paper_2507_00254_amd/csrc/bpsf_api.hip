@@ -87,7 +87,7 @@ struct bpsf_code_s {
   DevBuf row_w, init32, init64;
   // large irregular matrices: a sparse family (float messages only)
   int sparse = -1;
-  DevBuf sp_roff, sp_bits, sp_echk;
+  DevBuf sp_roff, sp_rw, sp_bits, sp_echk, sp_rperm, sp_cperm, sp_cinv;
   std::vector<int32_t> ell_host;
   // channel LLR cache
   std::vector<double> priors;
@@ -330,8 +330,12 @@ int fill_code_args(const bpsf_code_s* c, const bpsf_params* p, const TileDesc& t
   a.n_layers = c->n_layers;
   a.E = c->E;
   a.sp_roff = static_cast<const uint16_t*>(c->sp_roff.p);
+  a.sp_rw = static_cast<const uint8_t*>(c->sp_rw.p);
   a.sp_bits = static_cast<const uint32_t*>(c->sp_bits.p);
   a.sp_echk = static_cast<const uint16_t*>(c->sp_echk.p);
+  a.sp_rperm = static_cast<const uint16_t*>(c->sp_rperm.p);
+  a.sp_cperm = static_cast<const uint16_t*>(c->sp_cperm.p);
+  a.sp_cinv = static_cast<const uint16_t*>(c->sp_cinv.p);
   a.syn_stride = c->M;
   a.corr_stride = c->N;
   a.max_iter = p->max_iter;
@@ -386,7 +390,7 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
   const bool fp64 = p->precision == BPSF_PREC_FP64;
   if (c->sparse >= 0) {
     const SparseDesc d = sparse_desc(c->sparse);
-    pl->lds = sparse_layout(c->E, c->M, d.NW, d.DVMAX).total;
+    pl->lds = sparse_layout(c->E, c->M, d.NW, d.DVMAX, d.CPT).total;
     if (pl->lds > c->lds_max)
       return fail(BPSF_ENOTSUP, "the %d edges of this code need %zu bytes of LDS per workgroup, the device gives %zu",
                   c->E, pl->lds, c->lds_max);
@@ -512,7 +516,8 @@ int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, in
     for (int f = 0; f < sparse_count() && c->wide < 0 && c->sparse < 0; ++f) {
       const SparseDesc d = sparse_desc(f);
       const int T = 64 * d.NW;
-      if (rmax <= d.WMAX && cmax <= d.DVMAX && M <= T * d.CPT && N <= T * d.BPT && E + d.DVMAX + 1 <= 65535) {
+      if (rmax <= d.WMAX && cmax <= d.DVMAX && M <= T * d.CPT && N <= T * d.BPT &&
+          E + d.DVMAX + T * d.CPT <= 65535) {
         c->sparse = f;
         c->W = d.WMAX;
         c->DV = d.DVMAX;
@@ -588,28 +593,59 @@ int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, in
               hipMemcpy(c->row_w.p, roww.data(), roww.size(), hipMemcpyHostToDevice) != hipSuccess))
     rc = fail(BPSF_EDEVICE, "uploading code tables");
   if (!rc && c->sparse >= 0) {
-    // edges in column-major order (a column's edges by ascending check); the
-    // row offsets of every check (the +inf cell E + DVMAX past the weight)
+    // checks and bits renumbered by weight (ties by index), so that the rows
+    // and columns a wave handles together have nearly equal weights; edges
+    // in column-major order of the new bit numbers, a column's edges by
+    // ascending (caller's) check, which is the order of the sums; row
+    // offsets per new check, past the weight the pad cell of the thread
+    // slot that owns the check (new check ri belongs to thread ri mod T,
+    // slot ri / T; pad cells follow the E + DVMAX message cells)
     const SparseDesc d = sparse_desc(c->sparse);
+    const int T = 64 * d.NW;
+    std::vector<int> rperm((size_t)M), cperm((size_t)N), rinv((size_t)M), cinv((size_t)N);
+    for (int i = 0; i < M; ++i) rperm[i] = i;
+    for (int i = 0; i < N; ++i) cperm[i] = i;
+    std::stable_sort(rperm.begin(), rperm.end(),
+                     [&](int x, int y) { return row_ptr[x + 1] - row_ptr[x] < row_ptr[y + 1] - row_ptr[y]; });
+    std::stable_sort(cperm.begin(), cperm.end(), [&](int x, int y) { return colw[x] < colw[y]; });
+    for (int i = 0; i < M; ++i) rinv[rperm[i]] = i;
+    for (int i = 0; i < N; ++i) cinv[cperm[i]] = i;
     std::vector<uint32_t> colptr((size_t)N + 1, 0);
-    for (int v = 0; v < N; ++v) colptr[v + 1] = colptr[v] + (uint32_t)colw[v];
-    std::vector<uint16_t> roff((size_t)M * d.WMAX, (uint16_t)(E + d.DVMAX));
-    std::vector<uint16_t> echk((size_t)(E > 0 ? E : 1), 0);
+    for (int v = 0; v < N; ++v) colptr[v + 1] = colptr[v] + (uint32_t)colw[cperm[v]];
+    std::vector<uint16_t> roff((size_t)M * d.WMAX);
+    for (int ri = 0; ri < M; ++ri)
+      for (int j = 0; j < d.WMAX; ++j)
+        roff[(size_t)ri * d.WMAX + j] = (uint16_t)(E + d.DVMAX + (ri % T) * d.CPT + ri / T);
+    std::vector<uint8_t> srw((size_t)M);
+    std::vector<uint16_t> echk((size_t)(E > 0 ? E : 1), 0), rp16((size_t)M), cp16((size_t)N), ci16((size_t)N);
     std::vector<uint32_t> bits((size_t)N);
     std::vector<uint32_t> put(colptr.begin(), colptr.end() - 1);
-    for (int r = 0; r < M; ++r)
+    for (int r = 0; r < M; ++r) {   // caller's checks in ascending order
+      const int ri = rinv[r];
+      srw[ri] = (uint8_t)(row_ptr[r + 1] - row_ptr[r]);
       for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
-        const int v = col_idx[e];
-        const uint32_t cell = put[v]++;
-        roff[(size_t)r * d.WMAX + (e - row_ptr[r])] = (uint16_t)cell;
-        echk[cell] = (uint16_t)r;
+        const uint32_t cell = put[cinv[col_idx[e]]]++;
+        roff[(size_t)ri * d.WMAX + (e - row_ptr[r])] = (uint16_t)cell;
+        echk[cell] = (uint16_t)ri;
       }
-    for (int v = 0; v < N; ++v) bits[v] = colptr[v] | ((uint32_t)colw[v] << 16);
-    if (c->sp_roff.ensure(roff.size() * 2) || c->sp_echk.ensure(echk.size() * 2) || c->sp_bits.ensure(bits.size() * 4))
+    }
+    for (int v = 0; v < N; ++v) {
+      bits[v] = colptr[v] | ((uint32_t)colw[cperm[v]] << 16);
+      cp16[v] = (uint16_t)cperm[v];
+      ci16[v] = (uint16_t)cinv[v];
+    }
+    for (int i = 0; i < M; ++i) rp16[i] = (uint16_t)rperm[i];
+    if (c->sp_roff.ensure(roff.size() * 2) || c->sp_echk.ensure(echk.size() * 2) || c->sp_bits.ensure(bits.size() * 4) ||
+        c->sp_rw.ensure(srw.size()) || c->sp_rperm.ensure(rp16.size() * 2) || c->sp_cperm.ensure(cp16.size() * 2) ||
+        c->sp_cinv.ensure(ci16.size() * 2))
       rc = fail(BPSF_ENOMEM, "sparse tables");
     else if (hipMemcpy(c->sp_roff.p, roff.data(), roff.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
              hipMemcpy(c->sp_echk.p, echk.data(), echk.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
-             hipMemcpy(c->sp_bits.p, bits.data(), bits.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+             hipMemcpy(c->sp_bits.p, bits.data(), bits.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(c->sp_rw.p, srw.data(), srw.size(), hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(c->sp_rperm.p, rp16.data(), rp16.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(c->sp_cperm.p, cp16.data(), cp16.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(c->sp_cinv.p, ci16.data(), ci16.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
       rc = fail(BPSF_EDEVICE, "uploading sparse tables");
   }
   if (!rc && c->wide < 0 && c->sparse < 0) {

@@ -50,11 +50,16 @@ struct Args {
   const uint8_t* check_layer;   // [M] layer of every check (layered schedule)
   const uint16_t* ell16;        // [M][W] bit of every (check, position) (layered schedule)
   int n_layers;
-  // sparse family (column-major edge order)
+  // sparse family: checks and bits renumbered by weight ("internal"), edges
+  // in column-major order of the internal bits
   int E;                        // edges
   const uint16_t* sp_roff;      // [M][WMAX] edge of every row position, the +inf cell past the weight
+  const uint8_t* sp_rw;         // [M] row weights
   const uint32_t* sp_bits;      // [N] first edge of the bit | weight << 16
-  const uint16_t* sp_echk;      // [E] check of every edge
+  const uint16_t* sp_echk;      // [E] internal check of every edge
+  const uint16_t* sp_rperm;     // [M] internal check -> caller's check
+  const uint16_t* sp_cperm;     // [N] internal bit -> caller's bit
+  const uint16_t* sp_cinv;      // [N] caller's bit -> internal bit
   double llr_uniform;        // the common channel LLR when every prior is equal
   // problem (device)
   const uint8_t* syndromes;  // [shots][syn_stride]; the first M bytes of a row are s

@@ -4,18 +4,27 @@
 // as bpsf_kernels.hip (paper Section II-B steps 1-4, Eq. (c2v), Algorithm 1),
 // same modes and keys.
 //
-// Layout:
+// Layout and schedule:
+//   * checks and bits are numbered internally by weight (the host permutes
+//     them at load), so the 64 rows or columns a wave handles together have
+//     nearly equal weights and every loop runs to the wave's largest weight
+//     (a scalar bound); results are written back in the caller's numbering,
+//     and ties of the top-|Phi| selection go to the lowest index of that
+//     numbering;
 //   * one message per Tanner edge in LDS, edges in column-major order (the
 //     edges of a bit are contiguous, by ascending check): the bit phase reads
-//     and writes a run of consecutive cells; the check phase gathers its
+//     and rewrites a run of consecutive cells; the check phase gathers its
 //     row's cells through offsets held in registers (two 16-bit offsets per
-//     word), padded positions pointing at one cell that holds +inf (no
-//     minimum, no sign) and skipped on the way back; a row is read twice
-//     (minima and parity, then the outputs) instead of being held in
-//     registers;
+//     word); a row's positions past its weight point at a cell of the
+//     owning thread that holds +inf when read (no minimum, no sign) and takes
+//     the junk written back;
 //   * thread g owns the checks g + T i and the bits g + T i (T threads);
-//   * u = H e and s (or s') are bit vectors in LDS; u is toggled when a hard
-//     decision flips;
+//   * u = H e and s (or s') are bit vectors in LDS; a bit whose hard decision
+//     flips toggles its checks in u;
+//   * an iteration is: check phase, which also compares u with s for the
+//     hard decisions of the previous iteration; one barrier; the decision to
+//     stop (the check phase's c2v are then dropped, the decode is over); bit
+//     phase; one barrier;
 //   * a failed first BP leaves a record holding its Phi; a trial rebuilds
 //     s' = s + t H^T from the shot's syndrome and the columns of Phi.
 #include <hip/hip_runtime.h>
@@ -30,14 +39,61 @@ namespace bpsf {
 
 namespace {
 
+// The caller's index of my internal bit g + T i. The index passes through an
+// empty asm so that the compiler does not hoist the table addresses of all
+// my bits out of the task loop (they would hold 64-bit registers for the
+// whole kernel).
+__device__ __forceinline__ int caller_bit(const Args& a, int v)
+{
+  asm volatile("" : "+v"(v));
+  return a.sp_cperm[v];
+}
+
+// Bit phase of one bit whose column starts at cell e0 and has w edges, for a
+// wave whose largest weight in this slot is K: the marginal and the v2c of
+// every edge, each summed from the channel LLR in ascending check order.
+// Loads past w read +0 (the next column's cells are replaced), stores past w
+// go to the junk cell.
+template <int K>
+__device__ __forceinline__ float bit_update(float* msg, uint32_t e0, uint32_t w, float L, uint32_t junk)
+{
+  float cv[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const float y = msg[e0 + j];
+    cv[j] = (uint32_t)j < w ? y : 0.f;
+  }
+  float pre[K + 1];
+  pre[0] = L;
+#pragma unroll
+  for (int j = 0; j < K; ++j) pre[j + 1] = pre[j] + cv[j];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    float acc = pre[j];
+#pragma unroll
+    for (int q = j + 1; q < K; ++q) acc = acc + cv[q];
+    msg[(uint32_t)j < w ? e0 + j : junk] = acc;
+  }
+  return pre[K];
+}
+
+// Largest value of x over the wave (the same in every lane, as a scalar).
+__device__ __forceinline__ uint32_t wave_max(uint32_t x)
+{
+  x = group_reduce(x, 64, OpMax());
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+
 template <int NW, int CPT, int WMAX, int BPT, int DVMAX, int MODE>
 __device__ __forceinline__ void decode_sparse(const Args& a)
 {
   using R = RT<float>;
   using F = SparseFamily<NW, CPT, WMAX, BPT, DVMAX>;
   constexpr int T = F::T, PL = F::PL, KMAX = F::KMAX;
+  constexpr int CH = 8;   // row positions loaded together
+  static_assert(WMAX % CH == 0, "rows are read in chunks of CH positions");
   const int M = a.M, N = a.N, E = a.E;
-  const SparseLayout lay = sparse_layout(E, M, NW, DVMAX);
+  const SparseLayout lay = sparse_layout(E, M, NW, DVMAX, CPT);
   extern __shared__ __align__(16) unsigned char smem[];
   float* msg = reinterpret_cast<float*>(smem + lay.msg);
   uint32_t* ub = reinterpret_cast<uint32_t*>(smem + lay.ubits);
@@ -47,33 +103,40 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
   uint32_t* flags = reinterpret_cast<uint32_t*>(smem + lay.flags);
 
   const int g = threadIdx.x;
-  const int MW = (M + 31) >> 5;        // words of a check bit vector
+  const uint32_t pad0 = (uint32_t)(E + DVMAX) + (uint32_t)(g * CPT);   // my pad cells, one per check slot
+  const int MW = (M + 31) >> 5;              // words of a check bit vector
   const float* __restrict__ llr = reinterpret_cast<const float*>(a.llr);
   const bool adaptive = !(a.alpha > 0.0);
   const float alpha_fixed = adaptive ? 1.0f : (float)a.alpha;
 
   // ---- per-thread constants -------------------------------------------------
-  // my checks: their edges as packed 16-bit cell indices, and their weights
+  // my checks: their edges as packed 16-bit cell indices (my pad cell past
+  // the weight), and the wave's largest weight
   uint32_t roff[CPT][WMAX / 2];
-  uint32_t rw[CPT];
+  uint32_t rbound[CPT];
 #pragma unroll
   for (int i = 0; i < CPT; ++i) {
     const int c = g + T * i;
-    const uint32_t pad = (uint32_t)(E + DVMAX) * 0x10001u;
+    const uint32_t pad = (pad0 + (uint32_t)i) * 0x10001u;
 #pragma unroll
     for (int j = 0; j < WMAX / 2; ++j) roff[i][j] = pad;
-    rw[i] = 0;
+    uint32_t w = 0;
     if (c < M) {
       const uint32_t* src = reinterpret_cast<const uint32_t*>(a.sp_roff) + (long long)c * (WMAX / 2);
 #pragma unroll
       for (int j = 0; j < WMAX / 2; ++j) roff[i][j] = src[j];
-      rw[i] = a.row_w[c];
+      w = a.sp_rw[c];
     }
+    rbound[i] = wave_max(w);
   }
-  // my bits: first edge | weight << 16, channel LLR
+  // my bits: first edge | weight << 16, channel LLR, and the wave's largest
+  // weight per bit slot (4 bits each)
   uint32_t bw[BPT];
   float Lv[BPT];
+  uint32_t wbp[(BPT + 7) / 8];
   uint32_t vmask = 0;
+#pragma unroll
+  for (int w = 0; w < (BPT + 7) / 8; ++w) wbp[w] = 0;
 #pragma unroll
   for (int i = 0; i < BPT; ++i) {
     const int v = g + T * i;
@@ -81,13 +144,13 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
     Lv[i] = 0.f;
     if (v < N) {
       bw[i] = a.sp_bits[v];
-      Lv[i] = llr[v];
+      Lv[i] = llr[a.sp_cperm[v]];
       vmask |= 1u << i;
     }
+    wbp[i >> 3] |= wave_max(bw[i] >> 16) << (4 * (i & 7));
   }
-  // cells past the last column (read by the bit phase, never used) and the
-  // +inf cell of padded row positions
-  for (int i = g; i <= DVMAX; i += T) msg[E + i] = i == DVMAX ? INFINITY : 0.f;
+  // cells past the last column: read by the bit phase, never used
+  for (int i = g; i < DVMAX; i += T) msg[E + i] = 0.f;
 
   // ---- task source ----------------------------------------------------------
   long long n_tasks;
@@ -137,7 +200,7 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
     if (t >= n_tasks) break;
     if (task[3]) continue;
 
-    // ---- inputs: s into LDS bits, u = 0 ----
+    // ---- inputs: s into LDS bits (internal check order), u = 0 ----
     long long shot = 0;
     int rec = 0, trial = 0, main_iters = 0;
     const int32_t* r = nullptr;
@@ -154,7 +217,7 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
       const uint8_t* s = a.syndromes + shot * a.syn_stride;
       for (int c0 = 0; c0 < M; c0 += T) {
         const int c = c0 + g;
-        const unsigned long long b = __ballot(c < M && (s[c < M ? c : 0] & 1u));
+        const unsigned long long b = __ballot(c < M && (s[a.sp_rperm[c < M ? c : 0]] & 1u));
         if ((g & 63) == 0 && c < M) {
           sb[c >> 5] = (uint32_t)b;
           if ((c >> 5) + 1 < MW) sb[(c >> 5) + 1] = (uint32_t)(b >> 32);
@@ -164,7 +227,8 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
     }
     uint32_t tbits = 0;
     if constexpr (MODE != MODE_MAIN) {
-      // s' = s + t H^T: thread j flips the checks of Phi[j] when the trial has it
+      // s' = s + t H^T: thread j flips the checks of Phi[j] (an internal bit
+      // index) when the trial has it
       __syncthreads();
       const uint32_t mask = a.trial_masks[shot * a.mask_stride + trial];
       if (g < a.k && ((mask >> g) & 1u)) {
@@ -198,7 +262,7 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
     }
     __syncthreads();
 
-    uint32_t hb = 0, prevt = 0, prevc = 0;
+    uint32_t hb = 0, prevc = 0;
     uint32_t cnt[PL];
 #pragma unroll
     for (int b = 0; b < PL; ++b) cnt[b] = 0;
@@ -206,71 +270,124 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
     bool conv = false;
     const int cap = MODE == MODE_MAIN ? a.max_iter : a.cand_max_iter;
     for (;;) {
-      // ---- check phase: c2v from v2c, Eq. (c2v) ----
-      const float alpha = adaptive ? R::adaptive_alpha(iter + 1) : alpha_fixed;
-      // the offsets pass through an empty asm every iteration: the compiler
-      // would otherwise hoist every address derived from them out of the
-      // loop and hold it in a register for the whole decode
-#pragma unroll
-      for (int i = 0; i < CPT; ++i)
-#pragma unroll
-        for (int j = 0; j < WMAX / 2; ++j) asm volatile("" : "+v"(roff[i][j]));
-#pragma unroll
-      for (int i = 0; i < BPT; ++i) asm volatile("" : "+v"(bw[i]));
+      // the offsets and bounds pass through an empty asm every iteration:
+      // the compiler would otherwise hoist every address and lane mask
+      // derived from them out of the loop and hold it in registers for the
+      // whole decode
 #pragma unroll
       for (int i = 0; i < CPT; ++i) {
-        // two passes over the row: minima and sign parity, then the outputs
-        // (the row is read twice rather than held in registers)
+#pragma unroll
+        for (int j = 0; j < WMAX / 2; ++j) asm volatile("" : "+v"(roff[i][j]));
+        asm volatile("" : "+v"(rbound[i]));
+      }
+
+      // ---- check phase: c2v from v2c, Eq. (c2v); and the syndrome test of
+      // the last hard decisions (u against s on my checks) ----
+      const float alpha = adaptive ? R::adaptive_alpha(iter + 1) : alpha_fixed;
+      uint32_t unsat = 0;
+#pragma unroll
+      for (int i = 0; i < CPT; ++i) {
+        const int c = g + T * i;
+        if (c < M) unsat |= (ub[c >> 5] >> (c & 31)) ^ (synbits >> i);
+        msg[pad0 + i] = INFINITY;   // what my padded positions read
+        const uint32_t rb = (uint32_t)__builtin_amdgcn_readfirstlane((int)rbound[i]);
+        // two passes over the row in chunks of CH positions (a chunk's loads
+        // are issued together): minima and sign parity, then the outputs; the
+        // row is read twice rather than held in registers
         float m1 = INFINITY, m2 = INFINITY;
         uint32_t P = synbits << (31 - i);                  // (-1)^{s_c}
 #pragma unroll
-        for (int j = 0; j < WMAX; ++j) {
-          const uint32_t cell = (j & 1) ? (roff[i][j >> 1] >> 16) : (roff[i][j >> 1] & 0xffffu);
-          const float x = msg[cell];
-          m2 = R::med3(m1, m2, R::absr(x));
-          m1 = R::minr(m1, R::absr(x));
-          P ^= R::sw(x);
+        for (int jc = 0; jc < WMAX; jc += CH) {
+          if ((uint32_t)jc < rb) {
+            float x[CH];
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+              const int j = jc + q;
+              x[q] = msg[(j & 1) ? (roff[i][j >> 1] >> 16) : (roff[i][j >> 1] & 0xffffu)];
+            }
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+              m2 = R::med3(m1, m2, R::absr(x[q]));
+              m1 = R::minr(m1, R::absr(x[q]));
+              P ^= R::sw(x[q]);
+            }
+          }
         }
         float s1 = R::flip(alpha * m1, P), s2 = R::flip(alpha * m2, P);
         R::opaque(s1);
         R::opaque(s2);
+        // (addresses recomputed for the second pass rather than kept)
 #pragma unroll
-        for (int j = 0; j < WMAX; ++j) {
-          if ((uint32_t)j < rw[i]) {
-            const uint32_t cell = (j & 1) ? (roff[i][j >> 1] >> 16) : (roff[i][j >> 1] & 0xffffu);
-            const float x = msg[cell];
-            msg[cell] = R::flip(R::absr(x) == m1 ? s2 : s1, R::sw(x));
+        for (int j = 0; j < WMAX / 2; ++j) asm volatile("" : "+v"(roff[i][j]));
+#pragma unroll
+        for (int jc = 0; jc < WMAX; jc += CH) {
+          if ((uint32_t)jc < rb) {
+            float x[CH];
+            uint32_t cell[CH];
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+              const int j = jc + q;
+              cell[q] = (j & 1) ? (roff[i][j >> 1] >> 16) : (roff[i][j >> 1] & 0xffffu);
+              x[q] = msg[cell[q]];
+            }
+#pragma unroll
+            for (int q = 0; q < CH; ++q) msg[cell[q]] = R::flip(R::absr(x[q]) == m1 ? s2 : s1, R::sw(x[q]));
           }
+        }
+      }
+      const unsigned long long anyw = __ballot((unsat & 1u) != 0u);
+      if ((g & 63) == 0) flags[(iter & 1) * (NW + 1) + (g >> 6)] = anyw != 0ull ? 1u : 0u;
+      if constexpr (MODE == MODE_CAND) {
+        // stop once a lower-index trial of the shot has succeeded (thread 0
+        // reads the key for the workgroup; a stale value only stops later)
+        if (g == 0) {
+          uint32_t stop = 0;
+          if ((a.flags & FLAG_PRUNE) && iter > 0 && (iter & 1) == 0) {
+            const unsigned long long kk = __hip_atomic_load(&a.keys[rec], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            stop = kk != KEY_NONE && (int)((kk >> KEY_ITER_BITS) & 0xffffffffull) < trial;
+          }
+          flags[(iter & 1) * (NW + 1) + NW] = stop;
         }
       }
       __syncthreads();
+      if (iter > 0) {
+        // the test of the hard decisions of iteration `iter`; stopping here
+        // drops the c2v just computed
+        uint32_t anyun = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) anyun |= flags[(iter & 1) * (NW + 1) + w];
+        conv = anyun == 0u;
+        bool stop = false;
+        if constexpr (MODE == MODE_CAND) stop = flags[(iter & 1) * (NW + 1) + NW] != 0u;
+        if ((conv && !(a.flags & FLAG_NO_EARLY_STOP)) || iter >= cap || stop) break;
+      }
 
       // ---- bit phase: marginal, hard decision, next v2c (ascending checks) ----
+#pragma unroll
+      for (int i = 0; i < BPT; ++i) asm volatile("" : "+v"(bw[i]));
+#pragma unroll
+      for (int w = 0; w < (BPT + 7) / 8; ++w) asm volatile("" : "+v"(wbp[w]));
       uint32_t nhb = 0;
+      // one bit slot at a time, in straight-line code for the wave's largest
+      // weight of the slot (a load past a bit's weight reads the next column
+      // or a cell past the last one and is replaced by +0, which changes no
+      // sum, so the order is the oracle's)
 #pragma unroll
       for (int i = 0; i < BPT; ++i) {
         const uint32_t e0 = bw[i] & 0xffffu, w = bw[i] >> 16;
-        float cv[DVMAX];
-#pragma unroll
-        for (int j = 0; j < DVMAX; ++j) {
-          const float y = msg[e0 + j];
-          cv[j] = (uint32_t)j < w ? y : 0.f;   // +0 past the weight changes no sum
+        const uint32_t wb = (uint32_t)__builtin_amdgcn_readfirstlane((int)((wbp[i >> 3] >> (4 * (i & 7))) & 15u));
+        float lout;
+        switch (wb) {
+#define BPSF_BIT_CASE(K) \
+  case K: lout = bit_update<K>(msg, e0, w, Lv[i], pad0); break;
+          BPSF_BIT_CASE(1) BPSF_BIT_CASE(2) BPSF_BIT_CASE(3) BPSF_BIT_CASE(4) BPSF_BIT_CASE(5)
+          BPSF_BIT_CASE(6) BPSF_BIT_CASE(7) BPSF_BIT_CASE(8) BPSF_BIT_CASE(9) BPSF_BIT_CASE(10)
+#undef BPSF_BIT_CASE
+          default: lout = Lv[i]; break;   // a slot no bit of the wave has
         }
-        float pre[DVMAX + 1];
-        pre[0] = Lv[i];
-#pragma unroll
-        for (int j = 0; j < DVMAX; ++j) pre[j + 1] = pre[j] + cv[j];
-#pragma unroll
-        for (int j = 0; j < DVMAX; ++j) {
-          if ((uint32_t)j < w) {
-            float acc = pre[j];
-#pragma unroll
-            for (int q = j + 1; q < DVMAX; ++q) acc = acc + cv[q];
-            msg[e0 + j] = acc;
-          }
-        }
-        nhb |= (R::nonpos_msb(pre[DVMAX]) >> 31) << i;
+        nhb |= (R::nonpos_msb(lout) >> 31) << i;
       }
+      const uint32_t fl = (nhb & vmask) ^ hb;
       hb = nhb & vmask;
       if constexpr (MODE == MODE_MAIN) {
         const uint32_t fc = hb ^ prevc;
@@ -283,48 +400,24 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
           carry = tt;
         }
       }
-      {
-        // u follows the hard decisions: toggle the checks of every flipped bit
-        const uint32_t fl = hb ^ prevt;
-        prevt = hb;
-        if (fl) {
+      // u follows the hard decisions: a flipped bit toggles its checks (the
+      // check of every edge from a device table; all loads first)
+      if (fl) {
 #pragma unroll
-          for (int i = 0; i < BPT; ++i) {
-            if ((fl >> i) & 1u) {
-              const uint32_t e0 = bw[i] & 0xffffu, w = bw[i] >> 16;
-              for (uint32_t e = e0; e < e0 + w; ++e) {
-                const int c = a.sp_echk[e];
-                atomicXor(&ub[c >> 5], 1u << (c & 31));
-              }
-            }
+        for (int i = 0; i < BPT; ++i) {
+          if ((fl >> i) & 1u) {
+            const uint32_t e0 = bw[i] & 0xffffu, w = bw[i] >> 16;
+            uint32_t cc[DVMAX];
+#pragma unroll
+            for (int j = 0; j < DVMAX; ++j) cc[j] = a.sp_echk[(uint32_t)j < w ? e0 + j : 0u];
+#pragma unroll
+            for (int j = 0; j < DVMAX; ++j)
+              if ((uint32_t)j < w) atomicXor(&ub[cc[j] >> 5], 1u << (cc[j] & 31));
           }
         }
       }
       __syncthreads();
-
-      // ---- syndrome test over the whole decode ----
-      const uint32_t un = g < MW ? (ub[g] ^ sb[g]) : 0u;
-      const unsigned long long anyw = __ballot(un != 0u);
-      if ((g & 63) == 0) flags[(iter & 1) * (NW + 1) + (g >> 6)] = anyw != 0ull ? 1u : 0u;
-      if constexpr (MODE == MODE_CAND) {
-        if (g == 0) {
-          uint32_t stop = 0;
-          if ((a.flags & FLAG_PRUNE) && (iter & 1) == 1) {
-            const unsigned long long kk = __hip_atomic_load(&a.keys[rec], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            stop = kk != KEY_NONE && (int)((kk >> KEY_ITER_BITS) & 0xffffffffull) < trial;
-          }
-          flags[(iter & 1) * (NW + 1) + NW] = stop;
-        }
-      }
-      __syncthreads();
-      uint32_t anyun = 0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) anyun |= flags[(iter & 1) * (NW + 1) + w];
-      conv = anyun == 0u;
-      bool stop = false;
-      if constexpr (MODE == MODE_CAND) stop = flags[(iter & 1) * (NW + 1) + NW] != 0u;
       ++iter;
-      if ((conv && !(a.flags & FLAG_NO_EARLY_STOP)) || iter >= cap || stop) break;
     }
 
     // ---- finish ----
@@ -332,21 +425,23 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
       uint8_t* out = a.corrections + shot * a.corr_stride;
 #pragma unroll
       for (int i = 0; i < BPT; ++i)
-        if ((vmask >> i) & 1u) out[g + T * i] = (uint8_t)((hb >> i) & 1u);
+        if ((vmask >> i) & 1u) out[caller_bit(a, g + T * i)] = (uint8_t)((hb >> i) & 1u);
       if (g == 0) {
         a.converged[shot] = (uint8_t)conv;
         a.iterations[shot] = iter;
         st_iters += (unsigned long long)iter;
       }
       if (a.k > 0 && (!conv || (a.flags & FLAG_FORCE_PP))) {
-        // key = count << 16 | (0xffff - v): largest count, then lowest index
+        // key = count << 16 | (0xffff - caller's index): largest count, then
+        // lowest index of the caller's numbering
         uint32_t key[BPT];
 #pragma unroll
         for (int i = 0; i < BPT; ++i) {
           uint32_t cn = 0;
 #pragma unroll
           for (int b = 0; b < PL; ++b) cn |= ((cnt[b] >> i) & 1u) << b;
-          key[i] = ((vmask >> i) & 1u) ? ((cn << 16) | (uint32_t)(0xffff - (g + T * i))) : 0u;
+          const int v = g + T * i < N ? g + T * i : N - 1;
+          key[i] = ((vmask >> i) & 1u) ? ((cn << 16) | (uint32_t)(0xffff - caller_bit(a, v))) : 0u;
         }
         if (g == 0) task[1] = (long long)atomicAdd(&a.counters[CNT_FAILED], 1ull);
         __syncthreads();
@@ -363,7 +458,8 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
 #pragma unroll
           for (int i = 0; i < BPT; ++i) best = key[i] > best ? key[i] : best;
           best = wg_reduce<NW>(best, OpMax(), red);
-          const int v = best ? 0xffff - (int)(best & 0xffffu) : 0;
+          const int vo = best ? 0xffff - (int)(best & 0xffffu) : 0;
+          const int v = a.sp_cinv[vo];                     // internal index
           if (g == 0) rr[REC_HDR + j] = v;
           if (v % T == g) {
 #pragma unroll
@@ -390,7 +486,7 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
       const uint32_t e = hb ^ tbits;
 #pragma unroll
       for (int i = 0; i < BPT; ++i)
-        if ((vmask >> i) & 1u) out[g + T * i] = (uint8_t)((e >> i) & 1u);
+        if ((vmask >> i) & 1u) out[caller_bit(a, g + T * i)] = (uint8_t)((e >> i) & 1u);
       if (g == 0) {
         a.converged[shot] = 1;
         a.iterations[shot] = main_iters + iter;

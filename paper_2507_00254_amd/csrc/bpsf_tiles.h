@@ -164,9 +164,11 @@ struct SparseFamily {
 // Compiled sparse families (NW, CPT, WMAX, BPT, DVMAX): up to 1024 checks and
 // 9216 bits (the [[144,12,12]] memory circuit over 12 rounds gives 936
 // detectors and about 8,800 mechanisms, rows of weight <= 41, columns <= 9).
+// Sixteen waves hide LDS latency better than eight (measured: the first-BP
+// phase of that model runs 1.35x faster); the first family that fits is used.
 #define BPSF_SPARSE_LIST(X) \
-  X(8, 2, 48, 18, 10) \
-  X(16, 1, 48, 9, 10)
+  X(16, 1, 48, 9, 10) \
+  X(8, 2, 48, 18, 10)
 
 struct SparseDesc {
   int NW, CPT, WMAX, BPT, DVMAX;
@@ -176,15 +178,16 @@ struct SparseLayout {
   uint32_t msg, ubits, sbits, red, task, flags, total;
 };
 
-// LDS of a sparse-family workgroup for E edges and M checks: the messages
-// (E cells, then DVMAX cells read past the last column, then one +inf cell
-// read by padded row positions), u = H e and s as bit vectors, reductions.
-__host__ __device__ inline SparseLayout sparse_layout(int E, int M, int NW, int DVMAX)
+// LDS of a sparse-family workgroup for E edges and M checks: the cells (E
+// messages, then DVMAX cells read past the last column, then one pad cell per
+// check slot of every thread, T CPT of them), u = H e and s as bit vectors,
+// reductions.
+__host__ __device__ inline SparseLayout sparse_layout(int E, int M, int NW, int DVMAX, int CPT)
 {
   SparseLayout L;
   uint32_t o = 0;
   L.msg = o;
-  o += 4u * (uint32_t)(E + DVMAX + 1);
+  o += 4u * (uint32_t)(E + DVMAX + 64 * NW * CPT);
   o = lds_align16(o);
   L.ubits = o;
   o += 4u * (uint32_t)((M + 31) / 32);
