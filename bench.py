@@ -75,8 +75,12 @@ def _pmc_per_dispatch(csv_path: str, counter: str):
             if r["Counter_Name"] != counter:
                 continue
             kn = r["Kernel_Name"]
-            if "bpsf_kernel" in kn:
-                ph = "main" if ", 0, false>" in kn else ("trials" if ", 1, false>" in kn else "rerun")
+            if "bpsf_kernel<" in kn:
+                # template arguments: Real, IC, IV, W, DV, UL, MODE, TRACE, LAY
+                targs = [x.strip() for x in kn.split("bpsf_kernel<", 1)[1].split(">", 1)[0].split(",")]
+                if len(targs) > 8 and targs[8] == "true":
+                    continue
+                ph = {"0": "main", "1": "trials", "2": "rerun"}[targs[6]]
             elif "copy" in kn.lower():
                 ph = "copy"
             else:

@@ -19,6 +19,7 @@
 #include "../../include/bpsf.h"
 #include "bpsf_internal.h"
 #include "bpsf_tiles.h"
+#include "bpsf_sparse.h"
 
 using namespace bpsf;
 

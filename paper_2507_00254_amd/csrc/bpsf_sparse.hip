@@ -34,6 +34,7 @@
 #include "bpsf_device.h"
 #include "bpsf_internal.h"
 #include "bpsf_tiles.h"
+#include "bpsf_sparse.h"
 
 namespace bpsf {
 
