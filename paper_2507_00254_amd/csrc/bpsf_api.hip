@@ -88,6 +88,7 @@ struct bpsf_code_s {
   DevBuf row_w, init32, init64;
   // large irregular matrices: a sparse family (float messages only)
   int sparse = -1;
+  int sp_cells = 0;          // message cells (edges plus column padding)
   DevBuf sp_roff, sp_rw, sp_bits, sp_echk, sp_rperm, sp_cperm, sp_cinv;
   std::vector<int32_t> ell_host;
   // channel LLR cache
@@ -329,7 +330,7 @@ int fill_code_args(const bpsf_code_s* c, const bpsf_params* p, const TileDesc& t
   a.check_layer = static_cast<const uint8_t*>(c->check_layer.p);
   a.ell16 = static_cast<const uint16_t*>(c->ell16.p);
   a.n_layers = c->n_layers;
-  a.E = c->E;
+  a.E = c->sparse >= 0 ? c->sp_cells : c->E;   // the sparse kernels size their message cells by it
   a.sp_roff = static_cast<const uint16_t*>(c->sp_roff.p);
   a.sp_rw = static_cast<const uint8_t*>(c->sp_rw.p);
   a.sp_bits = static_cast<const uint32_t*>(c->sp_bits.p);
@@ -391,7 +392,7 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
   const bool fp64 = p->precision == BPSF_PREC_FP64;
   if (c->sparse >= 0) {
     const SparseDesc d = sparse_desc(c->sparse);
-    pl->lds = sparse_layout(c->E, c->M, d.NW, d.DVMAX, d.CPT).total;
+    pl->lds = sparse_layout(c->sp_cells, c->M, d.NW, d.DVMAX, d.CPT).total;
     if (pl->lds > c->lds_max)
       return fail(BPSF_ENOTSUP, "the %d edges of this code need %zu bytes of LDS per workgroup, the device gives %zu",
                   c->E, pl->lds, c->lds_max);
@@ -600,7 +601,8 @@ int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, in
     // ascending (caller's) check, which is the order of the sums; row
     // offsets per new check, past the weight the pad cell of the thread
     // slot that owns the check (new check ri belongs to thread ri mod T,
-    // slot ri / T; pad cells follow the E + DVMAX message cells)
+    // slot ri / T; pad cells follow the message cells and DVMAX cells read
+    // past the last column)
     const SparseDesc d = sparse_desc(c->sparse);
     const int T = 64 * d.NW;
     std::vector<int> rperm((size_t)M), cperm((size_t)N), rinv((size_t)M), cinv((size_t)N);
@@ -611,23 +613,62 @@ int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, in
     std::stable_sort(cperm.begin(), cperm.end(), [&](int x, int y) { return colw[x] < colw[y]; });
     for (int i = 0; i < M; ++i) rinv[rperm[i]] = i;
     for (int i = 0; i < N; ++i) cinv[cperm[i]] = i;
+    // A column of even weight takes one cell more: consecutive columns of a
+    // wave (equal weights) then start an odd number of cells apart, and the
+    // 32 lanes of a half-wave reading position j of their columns hit 32
+    // distinct LDS banks. Without room for the padding, none.
+    auto col_cells = [&](int w, bool pad) { return (uint32_t)(pad && (w % 2 == 0) ? w + 1 : w); };
+    uint32_t padded = 0;
+    for (int v = 0; v < N; ++v) padded += col_cells(colw[v], true);
+    const bool pad_cols = (int64_t)padded + d.DVMAX + (int64_t)T * d.CPT <= 65535;
     std::vector<uint32_t> colptr((size_t)N + 1, 0);
-    for (int v = 0; v < N; ++v) colptr[v + 1] = colptr[v] + (uint32_t)colw[cperm[v]];
+    for (int v = 0; v < N; ++v) colptr[v + 1] = colptr[v] + col_cells(colw[cperm[v]], pad_cols);
+    const int cells = (int)colptr[N];
+    c->sp_cells = cells;
+    auto pad_cell = [&](int ri) { return (uint32_t)(cells + d.DVMAX + (ri % T) * d.CPT + ri / T); };
     std::vector<uint16_t> roff((size_t)M * d.WMAX);
     for (int ri = 0; ri < M; ++ri)
-      for (int j = 0; j < d.WMAX; ++j)
-        roff[(size_t)ri * d.WMAX + j] = (uint16_t)(E + d.DVMAX + (ri % T) * d.CPT + ri / T);
+      for (int j = 0; j < d.WMAX; ++j) roff[(size_t)ri * d.WMAX + j] = (uint16_t)pad_cell(ri);
     std::vector<uint8_t> srw((size_t)M);
-    std::vector<uint16_t> echk((size_t)(E > 0 ? E : 1), 0), rp16((size_t)M), cp16((size_t)N), ci16((size_t)N);
+    std::vector<uint16_t> echk((size_t)(cells > 0 ? cells : 1), 0), rp16((size_t)M), cp16((size_t)N), ci16((size_t)N);
     std::vector<uint32_t> bits((size_t)N);
     std::vector<uint32_t> put(colptr.begin(), colptr.end() - 1);
+    std::vector<std::vector<uint32_t>> rcells((size_t)M);
     for (int r = 0; r < M; ++r) {   // caller's checks in ascending order
       const int ri = rinv[r];
       srw[ri] = (uint8_t)(row_ptr[r + 1] - row_ptr[r]);
       for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
         const uint32_t cell = put[cinv[col_idx[e]]]++;
-        roff[(size_t)ri * d.WMAX + (e - row_ptr[r])] = (uint16_t)cell;
+        rcells[(size_t)ri].push_back(cell);
         echk[cell] = (uint16_t)ri;
+      }
+    }
+    // The order of a row's positions is free (its minima and parity do not
+    // depend on it). For the 32 rows a half-wave reads together, position j
+    // of every row is chosen greedily among the row's unread cells so that
+    // the half-wave's reads at j fall in distinct LDS banks (cell mod 32)
+    // where it can; rows past their weight read their pad cells, whose banks
+    // are taken first.
+    for (int base = 0; base < M; base += 32) {
+      const int n = std::min(32, M - base);
+      int wmax = 0;
+      for (int l = 0; l < n; ++l) wmax = std::max(wmax, (int)rcells[(size_t)(base + l)].size());
+      std::vector<std::vector<uint32_t>> left(rcells.begin() + base, rcells.begin() + base + n);
+      for (int j = 0; j < wmax; ++j) {
+        uint32_t used = 0;
+        for (int l = 0; l < n; ++l)
+          if (left[(size_t)l].empty()) used |= 1u << (pad_cell(base + l) & 31u);
+        for (int l = 0; l < n; ++l) {
+          std::vector<uint32_t>& cand = left[(size_t)l];
+          if (cand.empty()) continue;
+          size_t pick = 0;
+          for (size_t q = 0; q < cand.size(); ++q)
+            if (!((used >> (cand[q] & 31u)) & 1u)) { pick = q; break; }
+          const uint32_t cell = cand[pick];
+          cand.erase(cand.begin() + (long)pick);
+          used |= 1u << (cell & 31u);
+          roff[(size_t)(base + l) * d.WMAX + j] = (uint16_t)cell;
+        }
       }
     }
     for (int v = 0; v < N; ++v) {
