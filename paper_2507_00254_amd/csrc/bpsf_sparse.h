@@ -26,11 +26,11 @@ struct SparseFamily {
 // Compiled sparse families (NW, CPT, WMAX, BPT, DVMAX): up to 1024 checks and
 // 9216 bits (the [[144,12,12]] memory circuit over 12 rounds gives 936
 // detectors and about 8,800 mechanisms, rows of weight <= 41, columns <= 9).
-// Sixteen waves hide LDS latency better than eight (measured: the first-BP
-// phase of that model runs 1.35x faster); the first family that fits is used.
+// Sixteen waves of one check and nine bits per thread: they hide LDS latency
+// better than eight waves of two checks and eighteen bits, which cover the
+// same shapes (measured: the first-BP phase of that model ran 1.35x faster).
 #define BPSF_SPARSE_LIST(X) \
-  X(16, 1, 48, 9, 10) \
-  X(8, 2, 48, 18, 10)
+  X(16, 1, 48, 9, 10)
 
 struct SparseDesc {
   int NW, CPT, WMAX, BPT, DVMAX;

@@ -54,15 +54,16 @@ __device__ __forceinline__ int caller_bit(const Args& a, int v)
 // wave whose largest weight in this slot is K: the marginal and the v2c of
 // every edge, each summed from the channel LLR in ascending check order.
 // Loads past w read +0 (the next column's cells are replaced), stores past w
-// go to the junk cell.
-template <int K>
+// go to the junk cell. UNI: every bit of the wave has weight K (no lane has
+// a position past its weight).
+template <int K, bool UNI>
 __device__ __forceinline__ float bit_update(float* msg, uint32_t e0, uint32_t w, float L, uint32_t junk)
 {
   float cv[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const float y = msg[e0 + j];
-    cv[j] = (uint32_t)j < w ? y : 0.f;
+    cv[j] = (UNI || (uint32_t)j < w) ? y : 0.f;
   }
   float pre[K + 1];
   pre[0] = L;
@@ -73,7 +74,7 @@ __device__ __forceinline__ float bit_update(float* msg, uint32_t e0, uint32_t w,
     float acc = pre[j];
 #pragma unroll
     for (int q = j + 1; q < K; ++q) acc = acc + cv[q];
-    msg[(uint32_t)j < w ? e0 + j : junk] = acc;
+    msg[(UNI || (uint32_t)j < w) ? e0 + j : junk] = acc;
   }
   return pre[K];
 }
@@ -135,6 +136,7 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
   uint32_t bw[BPT];
   float Lv[BPT];
   uint32_t wbp[(BPT + 7) / 8];
+  uint32_t unim = 0;   // slots whose bits all have the wave's largest weight
   uint32_t vmask = 0;
 #pragma unroll
   for (int w = 0; w < (BPT + 7) / 8; ++w) wbp[w] = 0;
@@ -148,7 +150,9 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
       Lv[i] = llr[a.sp_cperm[v]];
       vmask |= 1u << i;
     }
-    wbp[i >> 3] |= wave_max(bw[i] >> 16) << (4 * (i & 7));
+    const uint32_t wmax = wave_max(bw[i] >> 16), wmin = ~wave_max(~(bw[i] >> 16));
+    wbp[i >> 3] |= wmax << (4 * (i & 7));
+    unim |= (wmin == wmax ? 1u : 0u) << i;
   }
   // cells past the last column: read by the bit phase, never used
   for (int i = g; i < DVMAX; i += T) msg[E + i] = 0.f;
@@ -368,6 +372,8 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
       for (int i = 0; i < BPT; ++i) asm volatile("" : "+v"(bw[i]));
 #pragma unroll
       for (int w = 0; w < (BPT + 7) / 8; ++w) asm volatile("" : "+v"(wbp[w]));
+      asm volatile("" : "+v"(unim));
+      const uint32_t uni = (uint32_t)__builtin_amdgcn_readfirstlane((int)unim);
       uint32_t nhb = 0;
       // one bit slot at a time, in straight-line code for the wave's largest
       // weight of the slot (a load past a bit's weight reads the next column
@@ -379,8 +385,11 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
         const uint32_t wb = (uint32_t)__builtin_amdgcn_readfirstlane((int)((wbp[i >> 3] >> (4 * (i & 7))) & 15u));
         float lout;
         switch (wb) {
-#define BPSF_BIT_CASE(K) \
-  case K: lout = bit_update<K>(msg, e0, w, Lv[i], pad0); break;
+#define BPSF_BIT_CASE(K)                                             \
+  case K:                                                            \
+    lout = ((uni >> i) & 1u) ? bit_update<K, true>(msg, e0, w, Lv[i], pad0) \
+                             : bit_update<K, false>(msg, e0, w, Lv[i], pad0); \
+    break;
           BPSF_BIT_CASE(1) BPSF_BIT_CASE(2) BPSF_BIT_CASE(3) BPSF_BIT_CASE(4) BPSF_BIT_CASE(5)
           BPSF_BIT_CASE(6) BPSF_BIT_CASE(7) BPSF_BIT_CASE(8) BPSF_BIT_CASE(9) BPSF_BIT_CASE(10)
 #undef BPSF_BIT_CASE
