@@ -303,7 +303,7 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
         uint32_t P = synbits << (31 - i);                  // (-1)^{s_c}
 #pragma unroll
         for (int jc = 0; jc < WMAX; jc += CH) {
-          if ((uint32_t)jc < rb) {
+          if ((uint32_t)jc + CH <= rb) {
             float x[CH];
 #pragma unroll
             for (int q = 0; q < CH; ++q) {
@@ -316,6 +316,18 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
               m1 = R::minr(m1, R::absr(x[q]));
               P ^= R::sw(x[q]);
             }
+          } else if ((uint32_t)jc < rb) {
+            // the last, partial chunk: positions up to the wave's bound only
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+              const int j = jc + q;
+              if ((uint32_t)j < rb) {
+                const float x = msg[(j & 1) ? (roff[i][j >> 1] >> 16) : (roff[i][j >> 1] & 0xffffu)];
+                m2 = R::med3(m1, m2, R::absr(x));
+                m1 = R::minr(m1, R::absr(x));
+                P ^= R::sw(x);
+              }
+            }
           }
         }
         float s1 = R::flip(alpha * m1, P), s2 = R::flip(alpha * m2, P);
@@ -326,7 +338,7 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
         for (int j = 0; j < WMAX / 2; ++j) asm volatile("" : "+v"(roff[i][j]));
 #pragma unroll
         for (int jc = 0; jc < WMAX; jc += CH) {
-          if ((uint32_t)jc < rb) {
+          if ((uint32_t)jc + CH <= rb) {
             float x[CH];
             uint32_t cell[CH];
 #pragma unroll
@@ -337,6 +349,16 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
             }
 #pragma unroll
             for (int q = 0; q < CH; ++q) msg[cell[q]] = R::flip(R::absr(x[q]) == m1 ? s2 : s1, R::sw(x[q]));
+          } else if ((uint32_t)jc < rb) {
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+              const int j = jc + q;
+              if ((uint32_t)j < rb) {
+                const uint32_t cell = (j & 1) ? (roff[i][j >> 1] >> 16) : (roff[i][j >> 1] & 0xffffu);
+                const float x = msg[cell];
+                msg[cell] = R::flip(R::absr(x) == m1 ? s2 : s1, R::sw(x));
+              }
+            }
           }
         }
       }
