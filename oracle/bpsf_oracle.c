@@ -32,7 +32,8 @@
  *   - c2v magnitude is alpha * (minimum over the other edges), one rounding;
  *   - top(flip_count, k) orders by count descending, then index ascending;
  *   - trial vectors: either all 2^k subsets of Phi (subset index = bit mask,
- *     bit j <-> Phi[j]) or all subsets of weight 1..w_max in combination order;
+ *     bit j <-> Phi[j]) or all subsets of weight 1..w_max in combination order,
+ *     or the caller's list of masks (|Phi| up to 64);
  *   - every trial BP starts from zero messages with its own iteration count;
  *   - result selection: minimum Hamming weight of the undone correction (ties
  *     to the lower trial index), or the lowest-index successful trial;
@@ -317,10 +318,12 @@ static int priors_to_llr(const double *priors, int N, real *L)
     return 0;
 }
 
-static int check_params(const oracle_params *prm, int N)
+/* kmax: 24 for generated trial lists (2^k masks at most 2^24), up to 64 for
+ * a caller's list (a 64-bit mask per trial). */
+static int check_params(const oracle_params *prm, int N, int kmax)
 {
     if (prm->max_iter < 1 || prm->cand_max_iter < 0) return -1;
-    if (prm->k < 0 || prm->k > N || prm->k > 24) return -1;
+    if (prm->k < 0 || prm->k > N || prm->k > kmax) return -1;
     if (prm->cand_mode != 0 && prm->cand_mode != 1) return -1;
     if (prm->cand_mode == 1 && (prm->w_max < 1 || prm->w_max > prm->k)) return -1;
     if (prm->select_mode != 0 && prm->select_mode != 1) return -1;
@@ -331,13 +334,13 @@ static int check_params(const oracle_params *prm, int N)
 /* ---------------------------------------------------------- trial list -- */
 
 /* Number of trial vectors and, if masks != NULL, the masks in trial order. */
-static int64_t trial_masks(const oracle_params *prm, uint32_t *masks)
+static int64_t trial_masks(const oracle_params *prm, uint64_t *masks)
 {
     const int k = prm->k;
     if (k == 0) return 0;
     if (prm->cand_mode == 0) {
         int64_t n = (int64_t)1 << k;
-        if (masks) for (int64_t i = 0; i < n; i++) masks[i] = (uint32_t)i;
+        if (masks) for (int64_t i = 0; i < n; i++) masks[i] = (uint64_t)i;
         return n;
     }
     /* Weight 1, then weight 2, ...: combinations of positions in lexicographic order. */
@@ -347,8 +350,8 @@ static int64_t trial_masks(const oracle_params *prm, uint32_t *masks)
         for (int j = 0; j < wgt; j++) pos[j] = j;
         for (;;) {
             if (masks) {
-                uint32_t m = 0;
-                for (int j = 0; j < wgt; j++) m |= 1u << pos[j];
+                uint64_t m = 0;
+                for (int j = 0; j < wgt; j++) m |= 1ull << pos[j];
                 masks[n] = m;
             }
             n++;
@@ -380,7 +383,7 @@ typedef struct {
 } trial_record;
 
 static int bpsf_one(const graph *g, const uint8_t *s, const real *L, const oracle_params *prm,
-                    const uint32_t *masks, int64_t n_trials, bp_work *w, uint8_t *s2, uint8_t *best,
+                    const uint64_t *masks, int64_t n_trials, bp_work *w, uint8_t *s2, uint8_t *best,
                     uint8_t *corr, int32_t *phi_out, int32_t *flips_out, const bp_trace *tr,
                     trial_record *rec, shot_result *res)
 {
@@ -399,7 +402,7 @@ static int bpsf_one(const graph *g, const uint8_t *s, const real *L, const oracl
     if ((conv && !(prm->flags & OR_FORCE_PP)) || prm->k == 0) return 0;
 
     /* top(flip_count, |Phi|): count descending, index ascending. */
-    int32_t phi[32];
+    int32_t phi[64];
     uint8_t *t_vec = best;   /* trial vector t as a 0/1 array over the bits */
     memset(t_vec, 0, (size_t)N);
     for (int j = 0; j < prm->k; j++) {
@@ -419,10 +422,10 @@ static int bpsf_one(const graph *g, const uint8_t *s, const real *L, const oracl
     int32_t best_w = 0, best_it = 0;
     int64_t best_idx = -1;
     for (int64_t ti = 0; ti < n_trials; ti++) {
-        uint32_t mask = masks[ti];
+        uint64_t mask = masks[ti];
         memset(t, 0, (size_t)N);
         for (int j = 0; j < prm->k; j++)
-            if ((mask >> j) & 1u) t[phi[j]] = 1;
+            if ((mask >> j) & 1ull) t[phi[j]] = 1;
         /* s' = s + t H^T: row c of H dotted with t, added to s_c. */
         for (int c = 0; c < M; c++) {
             int par = s[c] & 1;
@@ -506,7 +509,15 @@ int64_t FN(oracle_num_trials)(const oracle_params *prm, uint32_t *masks_out)
 {
     if (prm->k < 0 || prm->k > 24) return -1;
     if (prm->cand_mode == 1 && (prm->w_max < 1 || prm->w_max > prm->k)) return -1;
-    return trial_masks(prm, masks_out);
+    const int64_t n = trial_masks(prm, NULL);
+    if (masks_out && n > 0) {
+        uint64_t *m = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+        if (!m) return -1;
+        trial_masks(prm, m);
+        for (int64_t i = 0; i < n; i++) masks_out[i] = (uint32_t)m[i];   /* k <= 24: no bit lost */
+        free(m);
+    }
+    return n;
 }
 
 /* BP-SF on one syndrome with every intermediate exposed (tests). */
@@ -517,11 +528,11 @@ int FN(oracle_bpsf_detail)(int32_t M, int32_t N, const int32_t *row_ptr, const i
                            int32_t *summary /* converged, iterations, main_iters, main_conv, winner */,
                            int64_t *trial_iter_total)
 {
-    if (M < 0 || N < 0 || !row_ptr || check_params(prm, N)) return -1;
+    if (M < 0 || N < 0 || !row_ptr || check_params(prm, N, 24)) return -1;
     graph g;
     if (graph_build(&g, M, N, row_ptr, col_idx)) return -1;
     int64_t nt = trial_masks(prm, NULL);
-    uint32_t *masks = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(nt > 0 ? nt : 1));
+    uint64_t *masks = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nt > 0 ? nt : 1));
     real *L = (real *)malloc(sizeof(real) * (size_t)(N > 0 ? N : 1));
     uint8_t *s2 = (uint8_t *)malloc((size_t)(M > N ? M : N) + 1);
     uint8_t *best = (uint8_t *)malloc((size_t)N + 1);
@@ -553,7 +564,7 @@ typedef struct {
     const uint8_t *syn;
     const real *L;
     const oracle_params *prm;
-    const uint32_t *masks;
+    const uint64_t *masks;
     int64_t n_trials, mask_stride, lo, hi;
     uint8_t *corr, *conv;
     int32_t *iters, *winner, *phi, *main_iters;
@@ -573,7 +584,7 @@ static void *batch_worker(void *arg)
     j->rc = 0;
     for (int64_t i = j->lo; i < j->hi; i++) {
         shot_result res;
-        int32_t phi_tmp[32];
+        int32_t phi_tmp[64];
         if (bpsf_one(j->g, j->syn + (size_t)i * M, j->L, j->prm, j->masks + i * j->mask_stride, j->n_trials,
                      &w, s2, best,
                      j->corr + (size_t)i * N, phi_tmp, NULL, NULL, NULL, &res)) { j->rc = -1; break; }
@@ -591,7 +602,7 @@ static void *batch_worker(void *arg)
 }
 
 static int run_batch(const graph *g, const uint8_t *syndromes, int64_t shots, const real *L,
-                     const oracle_params *prm, const uint32_t *masks, int64_t nt, int64_t mask_stride,
+                     const oracle_params *prm, const uint64_t *masks, int64_t nt, int64_t mask_stride,
                      uint8_t *corr, uint8_t *conv, int32_t *iters, int32_t *winner, int32_t *phi,
                      int32_t *main_iters, int64_t *trial_iters, int32_t nthreads)
 {
@@ -625,12 +636,12 @@ int FN(oracle_bpsf_batch)(int32_t M, int32_t N, const int32_t *row_ptr, const in
                           int32_t *winner, int32_t *phi, int32_t *main_iters, int64_t *trial_iters,
                           int32_t nthreads)
 {
-    if (M < 0 || N < 0 || shots < 0 || !row_ptr || check_params(prm, N)) return -1;
+    if (M < 0 || N < 0 || shots < 0 || !row_ptr || check_params(prm, N, 24)) return -1;
     if (shots == 0) return 0;
     graph g;
     if (graph_build(&g, M, N, row_ptr, col_idx)) return -1;
     int64_t nt = trial_masks(prm, NULL);
-    uint32_t *masks = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(nt > 0 ? nt : 1));
+    uint64_t *masks = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nt > 0 ? nt : 1));
     real *L = (real *)malloc(sizeof(real) * (size_t)(N > 0 ? N : 1));
     int rc = -1;
     if (masks && L && priors_to_llr(priors, N, L) == 0) {
@@ -647,17 +658,17 @@ int FN(oracle_bpsf_batch)(int32_t M, int32_t N, const int32_t *row_ptr, const in
 /* As oracle_bpsf_batch with the trial vectors given by the caller instead of
  * prm->cand_mode: shot i tries masks[i * mask_stride + t] for t < n_trials,
  * in that order (bit j <-> Phi[j]; bits at or above k are ignored). A stride
- * of 0 gives every shot the same list. */
-int FN(oracle_bpsf_batch_table)(int32_t M, int32_t N, const int32_t *row_ptr, const int32_t *col_idx,
-                                const uint8_t *syndromes, int64_t shots, const double *priors,
-                                const oracle_params *prm, const uint32_t *masks, int64_t n_trials,
-                                int64_t mask_stride, uint8_t *corr, uint8_t *conv, int32_t *iters,
-                                int32_t *winner, int32_t *phi, int32_t *main_iters, int64_t *trial_iters,
-                                int32_t nthreads)
+ * of 0 gives every shot the same list. 64-bit masks, |Phi| up to 64. */
+int FN(oracle_bpsf_batch_table64)(int32_t M, int32_t N, const int32_t *row_ptr, const int32_t *col_idx,
+                                  const uint8_t *syndromes, int64_t shots, const double *priors,
+                                  const oracle_params *prm, const uint64_t *masks, int64_t n_trials,
+                                  int64_t mask_stride, uint8_t *corr, uint8_t *conv, int32_t *iters,
+                                  int32_t *winner, int32_t *phi, int32_t *main_iters, int64_t *trial_iters,
+                                  int32_t nthreads)
 {
     oracle_params q = *prm;
     q.cand_mode = 0;   /* validated as such; the list comes from the caller */
-    if (M < 0 || N < 0 || shots < 0 || !row_ptr || check_params(&q, N)) return -1;
+    if (M < 0 || N < 0 || shots < 0 || !row_ptr || check_params(&q, N, 64)) return -1;
     if (n_trials < 0 || mask_stride < 0 || (n_trials > 0 && !masks)) return -1;
     if (shots == 0) return 0;
     graph g;
@@ -669,5 +680,25 @@ int FN(oracle_bpsf_batch_table)(int32_t M, int32_t N, const int32_t *row_ptr, co
                        main_iters, trial_iters, nthreads);
     free(L);
     graph_free(&g);
+    return rc;
+}
+
+/* The same with 32-bit masks (|Phi| up to 32): the list is widened. */
+int FN(oracle_bpsf_batch_table)(int32_t M, int32_t N, const int32_t *row_ptr, const int32_t *col_idx,
+                                const uint8_t *syndromes, int64_t shots, const double *priors,
+                                const oracle_params *prm, const uint32_t *masks, int64_t n_trials,
+                                int64_t mask_stride, uint8_t *corr, uint8_t *conv, int32_t *iters,
+                                int32_t *winner, int32_t *phi, int32_t *main_iters, int64_t *trial_iters,
+                                int32_t nthreads)
+{
+    if (prm->k > 32 || n_trials < 0 || mask_stride < 0 || shots < 0 || (n_trials > 0 && !masks)) return -1;
+    const int64_t n = mask_stride > 0 ? shots * mask_stride : n_trials;
+    uint64_t *wide = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+    if (!wide) return -1;
+    for (int64_t i = 0; i < n; i++) wide[i] = masks ? masks[i] : 0;
+    const int rc = FN(oracle_bpsf_batch_table64)(M, N, row_ptr, col_idx, syndromes, shots, priors, prm,
+                                                 n > 0 ? wide : NULL, n_trials, mask_stride, corr, conv, iters,
+                                                 winner, phi, main_iters, trial_iters, nthreads);
+    free(wide);
     return rc;
 }

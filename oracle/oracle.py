@@ -194,17 +194,19 @@ class OracleLib:
             rc = fn(C.c_int32(m), C.c_int32(n), _ptr(row_ptr, C.c_int32), _ptr(col_idx, C.c_int32),
                     _ptr(syn, C.c_uint8), C.c_int64(shots), _ptr(p, C.c_double), C.byref(prm), *outs)
         else:
-            tab = np.ascontiguousarray(masks, dtype=np.uint32)
+            # 64-bit masks when the list is 64-bit (|Phi| up to 64), else 32-bit
+            wide = np.asarray(masks).dtype in (np.uint64, np.int64)
+            tab = np.ascontiguousarray(masks, dtype=np.uint64 if wide else np.uint32)
             if tab.ndim == 1:
                 nt, stride = tab.shape[0], 0
             elif tab.ndim == 2 and tab.shape[0] == shots:
                 nt, stride = tab.shape[1], tab.shape[1]
             else:
                 raise ValueError("masks must be [n_trials] or [shots, n_trials]")
-            fn = getattr(self.lib(prec), f"oracle_bpsf_batch_table_{prec}")
+            fn = getattr(self.lib(prec), f"oracle_bpsf_batch_table{'64' if wide else ''}_{prec}")
             rc = fn(C.c_int32(m), C.c_int32(n), _ptr(row_ptr, C.c_int32), _ptr(col_idx, C.c_int32),
                     _ptr(syn, C.c_uint8), C.c_int64(shots), _ptr(p, C.c_double), C.byref(prm),
-                    _ptr(tab, C.c_uint32), C.c_int64(nt), C.c_int64(stride), *outs)
+                    _ptr(tab, C.c_uint64 if wide else C.c_uint32), C.c_int64(nt), C.c_int64(stride), *outs)
         if rc != 0:
             raise ValueError("oracle_bpsf_batch rejected its arguments")
         return {"correction": corr, "converged": conv, "iterations": iters, "winner": winner,

@@ -365,7 +365,38 @@ def pin_layered_ml_identity(O):
             assert int(r["correction"].sum()) == wmin
 
 
+def pin_wide_trial_masks(O):
+    """64-bit caller lists: a list widened from 32 bits gives the 32-bit
+    results; with |Phi| = 40, Phi is the first BP's 40 most-flipped bits by a
+    plain sort of its flip counts, and the single-bit trial 1 << 35 is plain
+    BP on s + H[:, Phi[35]] with that bit undone."""
+    h = codes.get_code("bb72").hx
+    _, syn = shots.make_shots(h, 0.08, 200, shots.stream_key(shots.MASTER_SEED, 973))
+    prm = Params(k=5, cand_mode=1, w_max=2)
+    tab = O.trial_masks(prm)
+    ref = O.bpsf_batch(h, syn, 0.08, prm, threads=4, masks=tab)
+    got = O.bpsf_batch(h, syn, 0.08, prm, threads=4, masks=tab.astype(np.uint64))
+    for f in ("correction", "converged", "iterations", "winner", "main_iterations", "trial_iterations"):
+        assert np.array_equal(got[f], ref[f]), f
+    big = Params(k=40, cand_max_iter=20)
+    res = O.bpsf_batch(h, syn, 0.08, big, threads=4, masks=np.array([1 << 35], np.uint64))
+    failed = np.nonzero(res["main_iterations"] == big.max_iter)[0]
+    assert len(failed) > 3
+    for i in failed[:8]:
+        flips = O.bpsf_detail(h, syn[i], 0.08, Params(k=1))["flips"]
+        order = sorted(range(len(flips)), key=lambda v: (-int(flips[v]), v))
+        assert list(res["phi"][i]) == order[:40]
+        v = int(res["phi"][i][35])
+        b = O.bp(h, syn[i] ^ h[:, v], 0.08, big, max_iter=big.cand_max_iter)
+        want = b["hard"].copy()
+        want[v] ^= 1
+        if b["converged"]:
+            assert res["converged"][i] == 1 and np.array_equal(res["correction"][i], want)
+        else:
+            assert res["converged"][i] == 0
+
+
 PINS = [pin_tree_min_sum, pin_tree_sum_product, pin_first_iteration_closed_form, pin_zero_syndrome,
         pin_half_prior, pin_ml_identity, pin_converged_invariant, pin_flip_counts, pin_empty_trial,
         pin_trial_vectors, pin_trial_results, pin_scale_invariance, pin_layered_tree, pin_layered_chain,
-        pin_layered_ml_identity]
+        pin_layered_ml_identity, pin_wide_trial_masks]

@@ -45,8 +45,10 @@ MUTANTS = [
      "w->v2c[e] = w->lout[g->col_idx[e]];"),
     ("layered_reverse_order", "const int c = g->order[i];", "const int c = g->order[g->M - 1 - i];"),
     ("layers_ignore_shared_bits", "if (c2 < c) used[layer[c2]] = 1;", "(void)c2;"),
-    ("trial_masks_skip_last", "for (int64_t i = 0; i < n; i++) masks[i] = (uint32_t)i;",
-     "for (int64_t i = 0; i < n; i++) masks[i] = (uint32_t)(i ? i - 1 : 0);"),
+    ("trial_masks_skip_last", "for (int64_t i = 0; i < n; i++) masks[i] = (uint64_t)i;",
+     "for (int64_t i = 0; i < n; i++) masks[i] = (uint64_t)(i ? i - 1 : 0);"),
+    ("wide_mask_bits_truncated", "if ((mask >> j) & 1ull) t[phi[j]] = 1;",
+     "if (((uint32_t)mask >> (j & 31)) & 1u) t[phi[j]] = 1;"),
 ]
 
 

@@ -30,3 +30,4 @@ def test_caller_trial_list_is_plumbing_only():
             got = O.bpsf_batch(h, syn, 0.07, prm, threads=4, masks=masks)
             for f in ("correction", "converged", "iterations", "winner", "main_iterations", "trial_iterations"):
                 assert np.array_equal(got[f], ref[f]), f
+
