@@ -76,7 +76,9 @@ typedef struct bpsf_code_s* bpsf_code;
 typedef struct {
   int32_t max_iter;       /* i_max of the first BP, 1..255 */
   int32_t cand_max_iter;  /* i_max of every trial BP, 1..4095 */
-  int32_t k;              /* |Phi|, 0..16; 0 = plain BP (no trials) */
+  int32_t k;              /* |Phi|, 0..16; 0 = plain BP (no trials); with BPSF_TRIALS_TABLE up to
+                             32 on codes of the sparse family, 64 with a 64-bit list
+                             (bpsf_set_trial_table64; Section V's complexity study uses 50) */
   int32_t cand_mode;      /* BPSF_TRIALS_* */
   int32_t w_max;          /* BPSF_TRIALS_WEIGHT_LE: largest trial weight, 1..k */
   int32_t select_mode;    /* BPSF_SELECT_* */
@@ -324,6 +326,13 @@ int bpsf_server_destroy(bpsf_server server);
  * clears the list. Takes effect on later calls.
  */
 int bpsf_set_trial_table(bpsf_code code, const uint32_t* masks, int64_t n_trials, int64_t stride);
+
+/*
+ * The same with 64-bit masks (device uint64), for |Phi| up to 64 on codes of
+ * the sparse family (the circuit-level matrices); other codes then fail with
+ * BPSF_ENOTSUP at decode time when k > 16. Replaces any 32-bit list.
+ */
+int bpsf_set_trial_table64(bpsf_code code, const uint64_t* masks, int64_t n_trials, int64_t stride);
 
 /* Shape of a loaded code: M, N, edges, row weight, column weight (host outs, any may be NULL). */
 int bpsf_code_info(bpsf_code code, int32_t* M, int32_t* N, int32_t* edges, int32_t* row_weight,

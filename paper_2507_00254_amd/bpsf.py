@@ -70,6 +70,7 @@ def _load():
     lib.bpsf_tile_options.argtypes = [vp, P(i32), i32]
     lib.bpsf_reserve.argtypes = [vp, i64, P(bpsf_params)]
     lib.bpsf_set_trial_table.argtypes = [vp, vp, i64, i64]
+    lib.bpsf_set_trial_table64.argtypes = [vp, vp, i64, i64]
     lib.bpsf_mix_reserve.argtypes = [vp, i64, P(bpsf_params)]
     lib.bpsf_set_tile.argtypes = [vp, i32, i32]
     lib.bpsf_autotune.argtypes = [vp, vp, P(C.c_double), i64, P(bpsf_params), i32, vp, P(bpsf_tuning)]
@@ -183,9 +184,10 @@ def bpsf_last_timing(handle) -> dict:
 
 
 def bpsf_set_trial_table(handle, masks=None) -> None:
-    """Trial list for TRIALS_TABLE: a device uint32 tensor [n_trials] (every
-    shot) or [shots, n_trials] (one list per shot), kept alive by the caller;
-    None clears it."""
+    """Trial list for TRIALS_TABLE: a device tensor [n_trials] (every shot) or
+    [shots, n_trials] (one list per shot) of 32-bit masks (int32 / uint32
+    bits), or of 64-bit masks (int64, |Phi| up to 64: bpsf_set_trial_table64),
+    kept alive by the caller; None clears it."""
     if masks is None:
         _check(LIB.bpsf_set_trial_table(C.c_void_p(handle), None, 0, 0))
         return
@@ -193,7 +195,12 @@ def bpsf_set_trial_table(handle, masks=None) -> None:
         raise ValueError("masks must be a contiguous device tensor")
     n = int(masks.shape[-1])
     stride = n if masks.dim() == 2 else 0
-    _check(LIB.bpsf_set_trial_table(C.c_void_p(handle), C.c_void_p(masks.data_ptr()), n, stride))
+    if masks.element_size() == 8:
+        _check(LIB.bpsf_set_trial_table64(C.c_void_p(handle), C.c_void_p(masks.data_ptr()), n, stride))
+    elif masks.element_size() == 4:
+        _check(LIB.bpsf_set_trial_table(C.c_void_p(handle), C.c_void_p(masks.data_ptr()), n, stride))
+    else:
+        raise ValueError("masks must hold 32-bit or 64-bit elements")
 
 
 def bpsf_reserve(handle, shots: int, params: bpsf_params) -> None:

@@ -99,8 +99,9 @@ struct bpsf_code_s {
   // trial masks cache
   int masks_k = -1, masks_mode = -1, masks_wmax = -1, n_trials = 0;
   // the caller's trial list (BPSF_TRIALS_TABLE)
-  const uint32_t* table = nullptr;
+  const uint32_t* table = nullptr;   // 32-bit masks, or 64-bit ones when table64
   int64_t table_n = 0, table_stride = 0;
+  bool table64 = false;
   DevBuf masks;
   // scratch
   DevBuf records, keys, counters;
@@ -186,7 +187,8 @@ int check_params(const bpsf_params* p)
 {
   if (!p) return fail(BPSF_EINVAL, "params is NULL");
   if (p->max_iter < 1 || p->max_iter > 255) return fail(BPSF_EINVAL, "max_iter must be in 1..255");
-  if (p->k < 0 || p->k > 16) return fail(BPSF_EINVAL, "k must be in 0..16");
+  if (p->k < 0 || p->k > (p->cand_mode == BPSF_TRIALS_TABLE ? 64 : 16))
+    return fail(BPSF_EINVAL, "k must be in 0..16 (0..64 with BPSF_TRIALS_TABLE)");
   if (p->k > 0 && (p->cand_max_iter < 1 || p->cand_max_iter >= (1 << KEY_ITER_BITS)))
     return fail(BPSF_EINVAL, "cand_max_iter must be in 1..4095");
   if (p->cand_mode != BPSF_TRIALS_ALL_SUBSETS && p->cand_mode != BPSF_TRIALS_WEIGHT_LE &&
@@ -350,6 +352,7 @@ int fill_code_args(const bpsf_code_s* c, const bpsf_params* p, const TileDesc& t
     a.n_trials = p->k > 0 ? (int)c->table_n : 0;
     a.trial_masks = c->table;
     a.mask_stride = c->table_stride;
+    if (c->table64) a.flags |= SPARSE_FLAG_MASKS64;
   } else {
     a.n_trials = c->n_trials;
     a.trial_masks = static_cast<const uint32_t*>(c->masks.p);
@@ -370,6 +373,10 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
     return fail(BPSF_ENOTSUP, "the layered schedule covers codes of the one-wave families with at most 254 layers");
   if (c->sparse >= 0 && p->precision != BPSF_PREC_FP32)
     return fail(BPSF_ENOTSUP, "codes of the sparse family decode with float messages only");
+  if (p->k > 16 && c->sparse < 0) return fail(BPSF_ENOTSUP, "|Phi| above 16 needs a code of the sparse family");
+  if (p->cand_mode == BPSF_TRIALS_TABLE && c->table64 && c->sparse < 0)
+    return fail(BPSF_ENOTSUP, "64-bit trial lists need a code of the sparse family");
+  if (p->k > 32 && !c->table64) return fail(BPSF_EINVAL, "|Phi| above 32 needs a 64-bit trial list");
   pl->wide = c->wide;
   pl->sparse = c->sparse;
   if (c->wide >= 0 || c->sparse >= 0) pl->tile = TileDesc{-1, 1};
@@ -908,6 +915,10 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
   int rc = check_params(p);
   if (rc) return rc;
   if (p->flags & BPSF_FLAG_LAYERED) return fail(BPSF_ENOTSUP, "mixed-code calls run the flooding schedule only");
+  if (p->k > 16) return fail(BPSF_ENOTSUP, "mixed-code calls take |Phi| up to 16");
+  if (p->cand_mode == BPSF_TRIALS_TABLE)
+    for (int i = 0; i < m->n; ++i)
+      if (m->codes[i]->table64) return fail(BPSF_ENOTSUP, "mixed-code calls take 32-bit trial lists only");
   if (shots < 0) return fail(BPSF_EINVAL, "shots < 0");
   if (shots > 0x7fffffffLL) return fail(BPSF_EINVAL, "at most 2^31-1 shots per call");
   if (!priors) return fail(BPSF_EINVAL, "priors is NULL");
@@ -1197,6 +1208,7 @@ int bpsf_mix_reserve(bpsf_mix m, int64_t shots, const bpsf_params* p)
   int rc = check_params(p);
   if (rc) return rc;
   if (shots < 1 || shots > 0x7fffffffLL) return fail(BPSF_EINVAL, "shots must be in 1..2^31-1");
+  if (p->k > 16) return fail(BPSF_ENOTSUP, "mixed-code calls take |Phi| up to 16");
   std::lock_guard<std::mutex> lk(m->mu);
   int stride = 0;
   for (int i = 0; i < m->n; ++i) {
@@ -1214,21 +1226,41 @@ int bpsf_mix_reserve(bpsf_mix m, int64_t shots, const bpsf_params* p)
   return 0;
 }
 
-int bpsf_set_trial_table(bpsf_code c, const uint32_t* masks, int64_t n_trials, int64_t stride)
+}  // extern "C"
+
+namespace {
+
+int set_table(bpsf_code c, const void* masks, int64_t n_trials, int64_t stride, bool wide)
 {
   if (!c) return fail(BPSF_EINVAL, "code is NULL");
   std::lock_guard<std::mutex> lk(c->mu);
   if (!masks) {
     c->table = nullptr;
     c->table_n = c->table_stride = 0;
+    c->table64 = false;
     return 0;
   }
   if (n_trials < 1 || n_trials > 0x7fffffffLL) return fail(BPSF_EINVAL, "n_trials must be in 1..2^31-1");
   if (stride != 0 && stride != n_trials) return fail(BPSF_EINVAL, "stride must be 0 or n_trials");
-  c->table = masks;
+  c->table = static_cast<const uint32_t*>(masks);
   c->table_n = n_trials;
   c->table_stride = stride;
+  c->table64 = wide;
   return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bpsf_set_trial_table(bpsf_code c, const uint32_t* masks, int64_t n_trials, int64_t stride)
+{
+  return set_table(c, masks, n_trials, stride, false);
+}
+
+int bpsf_set_trial_table64(bpsf_code c, const uint64_t* masks, int64_t n_trials, int64_t stride)
+{
+  return set_table(c, masks, n_trials, stride, true);
 }
 
 }  // extern "C"

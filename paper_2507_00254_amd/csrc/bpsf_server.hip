@@ -308,6 +308,7 @@ int bpsf_server_create(const bpsf_code* codes, int32_t n_codes, const double* co
   if (!batching && lanes != 1) return sfail(BPSF_EINVAL, "per-request mode runs one lane");
   if (max_batch_shots < 1 || max_batch_shots > (1 << 24)) return sfail(BPSF_EINVAL, "max_batch_shots in 1..2^24");
   if (params->flags & BPSF_FLAG_LAYERED) return sfail(BPSF_ENOTSUP, "the server runs the flooding schedule only");
+  if (params->k > 16) return sfail(BPSF_ENOTSUP, "the server takes |Phi| up to 16");
   bpsf_server_s* s = new (std::nothrow) bpsf_server_s;
   if (!s) return sfail(BPSF_ENOMEM, "handle");
   (void)hipGetDevice(&s->device);

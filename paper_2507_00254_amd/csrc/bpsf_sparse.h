@@ -19,7 +19,7 @@ template <int NW_, int CPT_, int WMAX_, int BPT_, int DVMAX_>
 struct SparseFamily {
   static constexpr int NW = NW_, CPT = CPT_, WMAX = WMAX_, BPT = BPT_, DVMAX = DVMAX_;
   static constexpr int T = 64 * NW;
-  static constexpr int PL = 8, KMAX = 16;
+  static constexpr int PL = 8, KMAX = 64;   // |Phi| up to 64 (records hold Phi only)
   static_assert(BPT <= 32 && WMAX % 2 == 0, "bit masks are 32 bits; row offsets come in pairs");
 };
 
@@ -67,6 +67,10 @@ __host__ __device__ inline SparseLayout sparse_layout(int E, int M, int NW, int 
   L.total = lds_align16(o);
   return L;
 }
+
+// Set by the host in Args::flags (above the caller's flags) when trial_masks
+// holds 64-bit masks.
+constexpr int SPARSE_FLAG_MASKS64 = 1 << 16;
 
 struct Args;
 int sparse_count();

@@ -235,8 +235,10 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
       // s' = s + t H^T: thread j flips the checks of Phi[j] (an internal bit
       // index) when the trial has it
       __syncthreads();
-      const uint32_t mask = a.trial_masks[shot * a.mask_stride + trial];
-      if (g < a.k && ((mask >> g) & 1u)) {
+      const long long mi = shot * a.mask_stride + trial;
+      const uint64_t mask = (a.flags & SPARSE_FLAG_MASKS64) ? reinterpret_cast<const uint64_t*>(a.trial_masks)[mi]
+                                                             : (uint64_t)a.trial_masks[mi];
+      if (g < a.k && ((mask >> g) & 1ull)) {
         const int v = r[REC_HDR + g];
         const uint32_t b = a.sp_bits[v];
         for (uint32_t e = b & 0xffffu; e < (b & 0xffffu) + (b >> 16); ++e) {
@@ -244,8 +246,8 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
           atomicXor(&sb[c >> 5], 1u << (c & 31));
         }
       }
-      for (int j = 0; j < KMAX; ++j) {
-        if (j < a.k && ((mask >> j) & 1u)) {
+      for (int j = 0; j < a.k; ++j) {
+        if ((mask >> j) & 1ull) {
           const int v = r[REC_HDR + j];
           if (v % T == g) tbits |= 1u << (v / T);
         }

@@ -115,3 +115,81 @@ def test_dem_logical_error_rate_is_the_oracles():
     fail = ((res @ dem.obs.T.astype(np.int64)) & 1).any(axis=1) | (g["converged"] == 0)
     print(f"logical failures {fail.sum()} / {len(syn)}", flush=True)
     assert fail.mean() < 0.05
+
+
+def _decode_table64(h, syn, pri, prm, masks):
+    """A decode with a caller list given as 64-bit masks when the list is
+    64-bit (bpsf_set_trial_table64), else as 32-bit masks."""
+    import torch
+    from paper_2507_00254_amd import bpsf as B
+    handle = B.bpsf_load_code(h)
+    try:
+        if masks.dtype == np.uint64:
+            d = torch.from_numpy(np.ascontiguousarray(masks).view(np.int64)).cuda()
+        else:
+            d = torch.from_numpy(np.ascontiguousarray(masks, dtype=np.uint32).view(np.int32)).cuda()
+        B.bpsf_set_trial_table(handle, d)
+        q = U.oracle_params(max_iter=prm.max_iter, cand_max_iter=prm.cand_max_iter, k=prm.k, cand_mode=2,
+                            select_mode=prm.select_mode, alpha=prm.alpha, flags=prm.flags)
+        return U.gpu_decode(h, syn, pri, q, handle=handle)
+    finally:
+        B.bpsf_free_code(handle)
+
+
+@pytest.mark.parametrize("k,w_max,n_s", [(50, 10, 10), (24, 6, 5)])
+def test_dem_large_phi(k, w_max, n_s):
+    """|Phi| above 16 on the circuit-level model: 50 with 64-bit masks (the
+    complexity study's |Phi| with w_max = 10, n_s = 10), 24 with 32-bit ones."""
+    from oracle import oracle as O
+    dem = _dem("bb144", 12, 0.003)
+    _, syn, _ = circuit.sample(dem, 200, shots.stream_key(shots.MASTER_SEED, 1407, k))
+    prm = U.oracle_params(max_iter=100, cand_max_iter=100, k=k, select_mode=1, alpha=0.0)
+    masks = trials.sample_trial_list(k, w_max, n_s, shots.stream_key(shots.MASTER_SEED, 1408, k))
+    assert masks.dtype == (np.uint64 if k > 32 else np.uint32)
+    g = _decode_table64(dem.h, syn, dem.priors, prm, masks)
+    o = O.bpsf_batch(dem.h, syn, dem.priors, prm, prec="f32", threads=8, masks=masks)
+    bad = U.mismatches(g, o)
+    print(f"|Phi| = {k}: {len(masks)} trials, failed {g['stats']['failed_shots']} mismatches {len(bad)}", flush=True)
+    assert len(bad) == 0 and g["stats"]["failed_shots"] > 0 and g["stats"]["errors"] == 0
+
+
+def test_large_phi_refused_elsewhere():
+    import torch
+    from paper_2507_00254_amd import bpsf as B
+    h72 = codes.get_code("bb72").hx
+    a = B.bpsf_load_code(h72)
+    dem = _dem("bb72", 6, 0.004)
+    sp = B.bpsf_load_code(dem.h)
+    try:
+        def run(handle, m, n, prm):
+            s = torch.zeros((2, m), dtype=torch.uint8, device="cuda")
+            c = torch.zeros((2, n), dtype=torch.uint8, device="cuda")
+            cv = torch.zeros(2, dtype=torch.uint8, device="cuda")
+            it = torch.zeros(2, dtype=torch.int32, device="cuda")
+            pri = np.full(n, 0.01)
+            B.bpsf_decode(handle, s, pri, prm, c, cv, it)
+        t32 = torch.ones(4, dtype=torch.int32, device="cuda")
+        t64 = torch.ones(4, dtype=torch.int64, device="cuda")
+        # a one-wave code: |Phi| above 16, or a 64-bit list
+        B.bpsf_set_trial_table(a, t32)
+        with pytest.raises(B.BpsfError) as ei:
+            run(a, 36, 72, B.make_params(k=20, cand_mode=B.TRIALS_TABLE))
+        assert ei.value.code == B.BPSF_ENOTSUP
+        B.bpsf_set_trial_table(a, t64)
+        with pytest.raises(B.BpsfError) as ei:
+            run(a, 36, 72, B.make_params(k=8, cand_mode=B.TRIALS_TABLE))
+        assert ei.value.code == B.BPSF_ENOTSUP
+        # the sparse family: |Phi| above 32 needs a 64-bit list; above 64 never
+        B.bpsf_set_trial_table(sp, t32)
+        with pytest.raises(B.BpsfError) as ei:
+            run(sp, dem.h.shape[0], dem.h.shape[1], B.make_params(k=40, cand_mode=B.TRIALS_TABLE, alpha=0.0))
+        assert ei.value.code == B.BPSF_EINVAL
+        with pytest.raises(B.BpsfError) as ei:
+            B.bpsf_num_trials(B.make_params(k=65, cand_mode=B.TRIALS_TABLE))
+        assert ei.value.code == B.BPSF_EINVAL
+        with pytest.raises(B.BpsfError) as ei:
+            B.bpsf_num_trials(B.make_params(k=17))
+        assert ei.value.code == B.BPSF_EINVAL
+    finally:
+        B.bpsf_free_code(sp)
+        B.bpsf_free_code(a)

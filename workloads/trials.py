@@ -27,9 +27,9 @@ def _subset(key: np.uint64, k: int, w: int, draw: int) -> int:
 
 
 def sample_trial_list(k: int, w_max: int, n_s: int, key: np.uint64, index: int = 0) -> np.ndarray:
-    """One list of trial masks (uint32)."""
-    if not (1 <= w_max <= k <= 16) or n_s < 1:
-        raise ValueError("need 1 <= w_max <= k <= 16 and n_s >= 1")
+    """One list of trial masks: uint32 for |Phi| = k <= 32, uint64 up to 64."""
+    if not (1 <= w_max <= k <= 64) or n_s < 1:
+        raise ValueError("need 1 <= w_max <= k <= 64 and n_s >= 1")
     out = []
     for w in range(1, w_max + 1):
         lk = stream_key(int(key), index, w)
@@ -54,7 +54,7 @@ def sample_trial_list(k: int, w_max: int, n_s: int, key: np.uint64, index: int =
             if m not in seen:
                 seen.append(m)
         out.extend(seen)
-    return np.array(out, np.uint32)
+    return np.array(out, np.uint32 if k <= 32 else np.uint64)
 
 
 def list_length(k: int, w_max: int, n_s: int) -> int:
@@ -62,6 +62,7 @@ def list_length(k: int, w_max: int, n_s: int) -> int:
 
 
 def sample_trial_table(k: int, w_max: int, n_s: int, key: np.uint64, shots: int) -> np.ndarray:
-    """One list per shot: uint32 [shots, list_length(k, w_max, n_s)]."""
+    """One list per shot: [shots, list_length(k, w_max, n_s)] (uint32, or
+    uint64 for k > 32)."""
     return np.stack([sample_trial_list(k, w_max, n_s, key, i) for i in range(shots)]) if shots else \
-        np.zeros((0, list_length(k, w_max, n_s)), np.uint32)
+        np.zeros((0, list_length(k, w_max, n_s)), np.uint32 if k <= 32 else np.uint64)
