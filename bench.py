@@ -298,7 +298,9 @@ def run_dem(args):
     8,784 mechanisms), 2x10^4 shots sampled from it at each of p = 0.001,
     0.002, 0.003; adaptive alpha, 100 first-BP iterations, |Phi| = 16 with
     n_s = 5 sampled trials per weight 1..6 (30 trials of 100 iterations),
-    first success kept with pruning; float messages (sparse kernel family)."""
+    first success kept with pruning; float messages (sparse kernel family).
+    A fourth point runs p = 0.003 with |Phi| = 50 and n_s = 10 per weight
+    1..10 (100 trials)."""
     import torch
 
     from paper_2507_00254_amd import bpsf as B
@@ -312,25 +314,33 @@ def run_dem(args):
     d_masks = torch.from_numpy(masks.view(np.int32)).cuda()
     prm = B.make_params(max_iter=100, cand_max_iter=100, k=16, cand_mode=B.TRIALS_TABLE, select_mode=1, alpha=0.0,
                         flags=B.FLAG_PRUNE, precision=B.PREC_FP32)
+    # the paper's complexity-study setting as a fourth point: |Phi| = 50,
+    # n_s = 10 per weight 1..10 (100 trials), p = 0.003
+    masks50 = trials.sample_trial_list(50, 10, 10, shots.stream_key(shots.MASTER_SEED, 1502))
+    d_masks50 = torch.from_numpy(masks50.view(np.int64)).cuda()
+    prm50 = B.make_params(max_iter=100, cand_max_iter=100, k=50, cand_mode=B.TRIALS_TABLE, select_mode=1,
+                          alpha=0.0, flags=B.FLAG_PRUNE, precision=B.PREC_FP32)
     rows = []
-    for p in (0.001, 0.002, 0.003):
+    for p, phi in ((0.001, 16), (0.002, 16), (0.003, 16), (0.003, 50)):
         dem = circuit.build_dem(c.hx, c.hz, 12, p)
         err, syn, obs = circuit.sample(dem, n, shots.stream_key(shots.MASTER_SEED, 1501, int(round(p * 1e5))))
         handle = B.bpsf_load_code(dem.h)
         edges = B.bpsf_code_info(handle)["edges"]
-        B.bpsf_set_trial_table(handle, d_masks)
+        B.bpsf_set_trial_table(handle, d_masks if phi == 16 else d_masks50)
         s = torch.from_numpy(syn).cuda()
         corr = torch.empty((n, dem.h.shape[1]), dtype=torch.uint8, device="cuda")
         conv = torch.empty((n,), dtype=torch.uint8, device="cuda")
         it = torch.empty((n,), dtype=torch.int32, device="cuda")
-        ms, avg, st = _timed_decodes(B, handle, s, dem.priors, prm, corr, conv, it, stream, args.steps, args.warmup)
+        ms, avg, st = _timed_decodes(B, handle, s, dem.priors, prm if phi == 16 else prm50, corr, conv, it, stream,
+                                     args.steps, args.warmup)
         iters = {"main": st["main_iterations"], "trials": st["trial_iterations"], "rerun": st["rerun_iterations"]}
         dom = max(avg, key=avg.get)
         ach = EDGE_BYTES * edges * iters[dom] / (avg[dom] * 1e-3) / 1e9
         res = (corr.cpu().numpy() ^ err).astype(np.int64)
         fail = ((res @ dem.obs.T.astype(np.int64)) & 1).any(axis=1) | (conv.cpu().numpy() == 0)
         ler = float(fail.mean())
-        rows.append({"p": p, "shots": n, "mechanisms": int(dem.h.shape[1]), "edges": edges,
+        rows.append({"p": p, "phi": phi, "trials": int(len(masks) if phi == 16 else len(masks50)),
+                     "shots": n, "mechanisms": int(dem.h.shape[1]), "edges": edges,
                      "ms_per_step": ms, "value": n / (ms * 1e-3), "phases_ms": avg,
                      "mean_latency_iterations": float(it.float().mean().item()),
                      "work": {**iters, "failed_shots": st["failed_shots"], "errors": st["errors"]},
@@ -344,8 +354,9 @@ def run_dem(args):
     print(json.dumps({"metric": "decoded shots/s, circuit-level [[144,12,12]] detector error model, d = 12",
                       "unit": "shots/s", "n_gpus": 1, "dtype": "f32",
                       "data": "synthetic (mechanisms sampled from a self-built detector error model)",
-                      "config": {"workload": "dem144_d12_2e4", "max_iter": 100, "k": 16, "trials": int(len(masks)),
-                                 "trial_iter": 100, "alpha": "adaptive", "select": "first", "prune": True},
+                      "config": {"workload": "dem144_d12_2e4", "max_iter": 100, "k": [16, 50],
+                                 "trials": [int(len(masks)), int(len(masks50))], "trial_iter": 100,
+                                 "alpha": "adaptive", "select": "first", "prune": True},
                       "points": rows}), flush=True)
 
 
