@@ -53,7 +53,10 @@ def test_dem_parity_generated_trials():
     for prm in (U.oracle_params(max_iter=60, cand_max_iter=30, k=6, alpha=0.0),
                 U.oracle_params(max_iter=60, cand_max_iter=30, k=10, cand_mode=1, w_max=2, alpha=0.0),
                 U.oracle_params(max_iter=60, cand_max_iter=30, k=6, alpha=0.625),
-                U.oracle_params(max_iter=40, k=0, alpha=0.0)):
+                U.oracle_params(max_iter=40, k=0, alpha=0.0),
+                U.oracle_params(max_iter=30, cand_max_iter=10, k=4, alpha=0.0, flags=1),     # no early stop
+                U.oracle_params(max_iter=30, cand_max_iter=10, k=4, alpha=0.0, flags=2),     # trials always
+                U.oracle_params(max_iter=60, cand_max_iter=30, k=6, alpha=0.0, select_mode=1, flags=4)):
         g = U.gpu_decode(dem.h, syn, dem.priors, prm)
         o = U.oracle_decode(dem.h, syn, dem.priors, prm, precision="f32")
         assert len(U.mismatches(g, o)) == 0, prm
