@@ -153,7 +153,7 @@ int pick_tile(const bpsf_code_s* c, TileDesc* out)
 size_t tile_lds(const bpsf_code_s* c, const TileDesc& t, bool fp64, bool uniform, bool layered = false)
 {
   const FamilyDesc f = family_desc(t.fam);
-  return lds_layout(fp64 ? 8 : 4, f.W, 64 * f.IC, c->M, c->N, f.DV, t.D, uniform, 8, layered, f.IV).total;
+  return lds_layout(fp64 ? 8 : 4, f.W, 64 * f.IC, c->M, c->N, f.DV, t.D, uniform, RING_META, layered, f.IV).total;
 }
 
 // Trial vectors of Algorithm 1 as k-bit masks over Phi, in trial order.
@@ -755,9 +755,14 @@ int bpsf_decode(bpsf_code c, const uint8_t* syndromes, const double* priors, int
   if (reset_counters(a.counters, CNT_WORDS, stream)) return fail(BPSF_EDEVICE, "counter reset launch");
   auto launch = [&](int mode) {
     if (pl.sparse >= 0) return sparse_dispatch(0, pl.sparse, mode, a, pl.lds, pl.grid[mode], stream, nullptr);
-    return pl.wide >= 0 ? wide_dispatch(0, pl.wide, fp64, mode, a, pl.lds, pl.grid[mode], stream, nullptr)
-                        : tile_dispatch(0, pl.tile, fp64, c->uniform, mode, false, a, pl.lds, pl.grid[mode], stream,
-                                        nullptr, (p->flags & BPSF_FLAG_LAYERED) != 0);
+    if (pl.wide >= 0) return wide_dispatch(0, pl.wide, fp64, mode, a, pl.lds, pl.grid[mode], stream, nullptr);
+    // no more waves than the phase can have chunks of tasks: every shot (a
+    // first BP or a re-run) or every trial of every shot
+    const long long most = mode == MODE_CAND ? shots * (long long)a.n_trials : shots;
+    const long long chunks = (most + a.chunk - 1) / a.chunk;
+    const int grid = chunks < pl.grid[mode] ? (int)std::max(1LL, chunks) : pl.grid[mode];
+    return tile_dispatch(0, pl.tile, fp64, c->uniform, mode, false, a, pl.lds, grid, stream, nullptr,
+                         (p->flags & BPSF_FLAG_LAYERED) != 0);
   };
   if (c->timing) HIP_OK(hipEventRecord(c->ev[0], st));
   if (launch(MODE_MAIN)) return fail(BPSF_EDEVICE, "first-BP launch failed");

@@ -20,9 +20,9 @@
 //     with IC odd the 32 lanes of a half-wave hit distinct banks. Bit-phase
 //     gathers of consecutive bits are mostly consecutive on quasi-cyclic
 //     codes;
-//   * the syndrome test is incremental: u = H e (one LDS word per check, laid
-//     out like the check items, bit 0 used) is toggled only when a hard
-//     decision flips, and a slot has converged when u equals its syndrome; a
+//   * the syndrome test is incremental: u = H e (16 LDS bits per lane, bit k
+//     for its check item k) is toggled only when a hard decision flips, and
+//     a slot has converged when u equals its syndrome; a
 //     refilled slot keeps its previous hard decisions as the toggle baseline,
 //     so u never needs re-initializing;
 //   * flip counts are bit-sliced counters (8 planes) in registers;
@@ -46,9 +46,10 @@ namespace bpsf {
 // left and returns once its slots have drained. UL: every bit has the same
 // channel LLR (uniform priors), held in a scalar. LAY: layered schedule (the
 // checks layer by layer, each reading and updating the bits' posteriors)
-// instead of flooding.
+// instead of flooding. own_first: the wave's first chunk of tasks follows
+// from its block index instead of the shared counter.
 template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE, bool TRACE, bool LAY>
-__device__ __forceinline__ void decode_code(const Args& a)
+__device__ __forceinline__ void decode_code(const Args& a, bool own_first)
 {
   using F = Family<IC, IV, W, DV>;
   using R = RT<Real>;
@@ -64,11 +65,15 @@ __device__ __forceinline__ void decode_code(const Args& a)
   extern __shared__ __align__(16) unsigned char smem[];
   const LdsLayout lay = lds_layout(sizeof(Real), W, CI, a.M, a.N, DV, D, UL, META, LAY, IV);
   Real* msg = reinterpret_cast<Real*>(smem + lay.msg);
+  // u = H e: lane g's 16 bits hold its check items (bit k = item k); XORed
+  // as 32-bit words, read as one u16 per lane
   uint32_t* uw = reinterpret_cast<uint32_t*>(smem + lay.resid);
+  const uint16_t* uw16 = reinterpret_cast<const uint16_t*>(smem + lay.resid);
+  // checks of every bit, as (owner lane within the slot) << 4 | item
   uint16_t* chk = reinterpret_cast<uint16_t*>(smem + lay.chk);
   Real* lrow = reinterpret_cast<Real*>(smem + lay.lrow);
   int32_t* ring_meta = reinterpret_cast<int32_t*>(smem + lay.ring_meta);
-  uint32_t* ring_syn = reinterpret_cast<uint32_t*>(smem + lay.ring_syn);
+  uint16_t* ring_syn = reinterpret_cast<uint16_t*>(smem + lay.ring_syn);
   uint32_t* ring_tb = reinterpret_cast<uint32_t*>(smem + lay.ring_tb);
   Real* lpost = reinterpret_cast<Real*>(smem + lay.lpost);          // LAY: [slot][G*IV] posteriors
   uint16_t* ellw = reinterpret_cast<uint16_t*>(smem + lay.ellw);    // LAY: [M][W] bit of each edge
@@ -82,18 +87,43 @@ __device__ __forceinline__ void decode_code(const Args& a)
   const bool adaptive = !(a.alpha > 0.0);
   const Real alpha_fixed = R::from_double(adaptive ? 1.0 : a.alpha);
 
+  // ---- task source ---------------------------------------------------------
+  long long n_tasks;
+  unsigned long long* next_ctr;
+  if constexpr (MODE == MODE_MAIN) {
+    n_tasks = a.task_count ? (long long)__atomic_load_n(a.task_count, __ATOMIC_RELAXED) : a.shots;
+    next_ctr = &a.counters[CNT_MAIN_NEXT];
+  } else if constexpr (MODE == MODE_CAND) {
+    n_tasks = (long long)__atomic_load_n(&a.counters[CNT_FAILED], __ATOMIC_RELAXED) * a.n_trials;
+    next_ctr = &a.counters[CNT_CAND_NEXT];
+  } else {
+    n_tasks = (long long)__atomic_load_n(&a.counters[CNT_FAILED], __ATOMIC_RELAXED);
+    next_ctr = &a.counters[CNT_EMIT_NEXT];
+  }
+  n_tasks = bcast0ll(n_tasks);
+  // own_first: wave b's first chunk is tasks [b * chunk, (b + 1) * chunk)
+  // and the counter hands out the rest after gridDim.x chunks, so a wave with
+  // nothing to do leaves before touching LDS or the counter (small calls
+  // launch many such waves)
+  if (own_first && (long long)blockIdx.x * a.chunk >= n_tasks) return;
+  bool first_chunk = own_first;
+
   // ---- per-code tables into LDS ------------------------------------------
   __syncthreads();   // a previous code's phase may still be reading them
   {
     // as 32-bit words (the device table is padded to a whole word), several
-    // loads in flight per lane
+    // loads in flight per lane; check c becomes (c / IC) << 4 | c % IC
     const uint32_t* src = reinterpret_cast<const uint32_t*>(a.var_chk);
     uint32_t* dst = reinterpret_cast<uint32_t*>(chk);
     const int nw = (N * DV + 1) >> 1;
+    auto own = [](uint32_t c) { return ((c / IC) << 4) | (c % IC); };
 #pragma unroll 8
-    for (int i = lane; i < nw; i += 64) dst[i] = src[i];
+    for (int i = lane; i < nw; i += 64) {
+      const uint32_t w = src[i];
+      dst[i] = own(w & 0xffffu) | (own(w >> 16) << 16);
+    }
   }
-  for (int i = lane; i < CI; i += 64) uw[i] = 0u;
+  if (lane < 32) uw[lane] = 0u;
   if constexpr (LAY) {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(a.ell16);
     uint32_t* dst = reinterpret_cast<uint32_t*>(ellw);
@@ -127,7 +157,8 @@ __device__ __forceinline__ void decode_code(const Args& a)
       if constexpr (!UL) Lv[k] = llr[v];
 #pragma unroll
       for (int j = 0; j < DV; ++j) {
-        const int c = chk[v * DV + j];
+        const int t = chk[v * DV + j];
+        const int c = (t >> 4) * IC + (t & 15);
         const int p = a.var_pos[v * DV + j];
         off[k][j] = lay.msg + (uint32_t)sizeof(Real) * (uint32_t)(p * CI + d * MS + c);
       }
@@ -168,20 +199,6 @@ __device__ __forceinline__ void decode_code(const Args& a)
 
   unsigned long long st_iters = 0, st_conv = 0, st_err = 0;
 
-  // ---- task source ---------------------------------------------------------
-  long long n_tasks;
-  unsigned long long* next_ctr;
-  if constexpr (MODE == MODE_MAIN) {
-    n_tasks = a.task_count ? (long long)__atomic_load_n(a.task_count, __ATOMIC_RELAXED) : a.shots;
-    next_ctr = &a.counters[CNT_MAIN_NEXT];
-  } else if constexpr (MODE == MODE_CAND) {
-    n_tasks = (long long)__atomic_load_n(&a.counters[CNT_FAILED], __ATOMIC_RELAXED) * a.n_trials;
-    next_ctr = &a.counters[CNT_CAND_NEXT];
-  } else {
-    n_tasks = (long long)__atomic_load_n(&a.counters[CNT_FAILED], __ATOMIC_RELAXED);
-    next_ctr = &a.counters[CNT_EMIT_NEXT];
-  }
-  n_tasks = bcast0ll(n_tasks);
   const int rstride = a.rec_stride;
 
   int head = 0, tail = 0;                 // ring positions (monotonic)
@@ -207,8 +224,14 @@ __device__ __forceinline__ void decode_code(const Args& a)
     if (exhausted || pend_n != 0 || (tail - head) > D) return;
     if (cnext >= cend) {
       long long base = 0;
-      if (lane == 0) base = (long long)atomicAdd(next_ctr, (unsigned long long)a.chunk);
-      base = bcast0ll(base);
+      if (first_chunk) {
+        base = (long long)blockIdx.x * a.chunk;
+        first_chunk = false;
+      } else {
+        if (lane == 0) base = (long long)atomicAdd(next_ctr, (unsigned long long)a.chunk);
+        base = bcast0ll(base);
+        if (own_first) base += (long long)gridDim.x * a.chunk;
+      }
       if (base >= n_tasks) { exhausted = true; return; }
       cnext = base;
       cend = base + a.chunk < n_tasks ? base + a.chunk : n_tasks;
@@ -523,21 +546,27 @@ __device__ __forceinline__ void decode_code(const Args& a)
     {
       uint32_t f = hb ^ prevt;
       prevt = hb;
+      int ubase = d * (G >> 1);   // my slot's first word of u
+      asm volatile("" : "+v"(ubase));
       while (f) {
         const int k = __builtin_ctz(f);
         f &= f - 1u;
         const int v = q + (k << LG);
 #pragma unroll
-        for (int i = 0; i < DV; ++i) atomicXor(&uw[d * MS + chk[v * DV + i]], 1u);
+        for (int i = 0; i < DV; ++i) {
+          const uint32_t t = chk[v * DV + i];
+          atomicXor(&uw[ubase + (t >> 5)], 1u << (t & 31u));
+        }
       }
     }
     __syncthreads();
 
     // ---- syndrome test of every slot: u == s on all its checks ----
-    uint32_t un = 0;
-#pragma unroll
-    for (int k = 0; k < IC; ++k) un |= uw[cbase + k] ^ (synbits >> k);
-    un &= 1u;
+    // (the lane index through an opaque copy: its LDS address is not worth a
+    // register across the loop)
+    int ul = lane;
+    asm volatile("" : "+v"(ul));
+    const uint32_t un = ((uint32_t)uw16[ul] ^ synbits) & ((1u << IC) - 1u);
     const unsigned long long ub = __ballot(un != 0u);
     const unsigned long long gm = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
     const bool conv = ((ub >> (d * G)) & gm) == 0ull;
@@ -576,16 +605,8 @@ __device__ __forceinline__ void decode_code(const Args& a)
         }
         const bool need = fin && a.k > 0 && (!conv || (a.flags & FLAG_FORCE_PP));
         if (__ballot(need) != 0ull) {
-          // flip counts of my bits; key = count << 16 | (0xffff - v): largest
-          // count first, then lowest index
-          uint32_t key[IV];
-#pragma unroll
-          for (int k = 0; k < IV; ++k) {
-            uint32_t cn = 0;
-#pragma unroll
-            for (int b = 0; b < PL; ++b) cn |= ((cnt[b] >> k) & 1u) << b;
-            key[k] = ((vmask >> k) & 1u) ? ((cn << 16) | (uint32_t)(0xffff - (q + Gf * k))) : 0u;
-          }
+          // my bits not yet taken into Phi
+          uint32_t avail = vmask;
           int f = 0;
           if (need && q == 0) {
             f = (int)atomicAdd(&a.counters[CNT_FAILED], 1ull);
@@ -606,31 +627,35 @@ __device__ __forceinline__ void decode_code(const Args& a)
             }
             r[REC_HDR + q] = (int32_t)synbits;
           }
-          // top(flip_count, |Phi|), one bit per round
+          // top(flip_count, |Phi|), one bit per round: the largest count
+          // first, then the lowest index. My candidate comes from the
+          // bit-sliced counts, highest plane first (the set of my available
+          // bits with the largest count, and that count); its key is
+          // count << 16 | (0xffff - v), and the slot's maximum key wins.
           for (int j = 0; j < a.k; ++j) {
-            uint32_t best = 0;
+            uint32_t cand = avail, cn = 0;
 #pragma unroll
-            for (int k = 0; k < IV; ++k) best = key[k] > best ? key[k] : best;
+            for (int b = PL - 1; b >= 0; --b) {
+              const uint32_t c1 = cand & cnt[b];
+              cand = c1 ? c1 : cand;
+              cn |= c1 ? (1u << b) : 0u;
+            }
+            uint32_t best = cand ? (cn << 16) | (uint32_t)(0xffff - (q + Gf * __builtin_ctz(cand))) : 0u;
             best = group_reduce(best, G, OpMax());
             const int v = best ? 0xffff - (int)(best & 0xffffu) : 0;   // best > 0 while k <= N
             // my share of column v: my checks among its DV checks, and v itself
             uint32_t tw = 0;
 #pragma unroll
             for (int i = 0; i < DV; ++i) {
-              const int c = chk[v * DV + i];
-              const int owner = c / IC;
-              if (owner == q) tw ^= 1u << (c - owner * IC);
+              const int t = chk[v * DV + i];
+              if ((t >> 4) == q) tw ^= 1u << (t & 15);
             }
             if ((v & (G - 1)) == q) tw |= (uint32_t)((v >> LG) + 1) << 16;
             if (need) {
               r[REC_HDR + G + j * G + q] = (int32_t)tw;
               if (q == 0) r[REC_HDR + G + a.k * G + j] = v;
             }
-            if ((v & (G - 1)) == q) {
-#pragma unroll
-              for (int k = 0; k < IV; ++k)
-                if (q + Gf * k == v) key[k] = 0u;
-            }
+            if ((v & (G - 1)) == q) avail &= ~(1u << (v >> LG));
           }
         }
       } else if constexpr (MODE == MODE_CAND) {
@@ -677,10 +702,17 @@ __device__ __forceinline__ void decode_code(const Args& a)
   if (lane == 0) atomicAdd(&a.counters[ST_WAVES], 1ull);
 }
 
+// Waves per SIMD the register allocator keeps room for: three for the float
+// kernels of the row-weight-6 family with uniform priors, whose LDS allows ten
+// waves per CU (a few registers over the limit would halve that to eight)
+template <typename Real, int W, bool UL, bool TRACE, bool LAY>
+constexpr int min_waves_per_simd() { return (sizeof(Real) == 4 && W == 6 && UL && !TRACE && !LAY) ? 3 : 1; }
+
 template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE, bool TRACE, bool LAY>
-__global__ __launch_bounds__(64) void bpsf_kernel(Args a)
+__global__ __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(min_waves_per_simd<Real, W, UL, TRACE, LAY>()))) void bpsf_kernel(Args a)
 {
-  decode_code<Real, IC, IV, W, DV, UL, MODE, TRACE, LAY>(a);
+  decode_code<Real, IC, IV, W, DV, UL, MODE, TRACE, LAY>(a, true);
 }
 
 // ------------------------------------------------------- mixed launches --
@@ -758,7 +790,8 @@ __global__ __launch_bounds__(64) void bpsf_mixed_kernel(const MixArgs m)
       rem = nt - bcast0ll(t);
     }
     if (rem <= 0) continue;
-    decode_code<Real, IC, IV, W, DV, UL, MODE, false, false>(m.code[c]);
+    // (the mixed kernel counts taken tasks by the counter: no static chunk)
+    decode_code<Real, IC, IV, W, DV, UL, MODE, false, false>(m.code[c], false);
   }
 }
 

@@ -17,12 +17,16 @@ namespace bpsf {
 // CI = 64 * IC entries. With IC = 1 (mod 8), MS = G (mod 32) for every G >= 4,
 // so the 32 lanes of each half-wave hit 32 distinct banks in the check phase,
 // and CI does not depend on D.
+// ints per ring entry header: shot (two words for the first BP), record,
+// trial, first-BP iterations
+constexpr int RING_META = 5;
+
 template <int IC_, int IV_, int W_, int DV_>
 struct Family {
   static constexpr int IC = IC_, IV = IV_, W = W_, DV = DV_;
   static constexpr int CI = 64 * IC;   // message entries per edge position
   static constexpr int PL = 8;         // bit planes of flip_count
-  static constexpr int META = 8;       // ints per ring entry header
+  static constexpr int META = RING_META;
   static constexpr int KMAX = 16;      // largest |Phi|
   static_assert(IC % 8 == 1, "IC = 1 (mod 8) keeps check-phase accesses free of bank conflicts");
   static_assert(IC <= 16 && IV <= 32, "items per lane must fit the 16-bit column masks and 32-bit bit masks");
@@ -66,8 +70,8 @@ __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int W, int CI, i
   L.msg = o;                                           // W x CI messages + 64-entry sink
   o += (uint32_t)real_bytes * (uint32_t)(W * CI + 64);
   o = lds_align16(o);
-  L.resid = o;                                         // u = H e, one word per check entry of every slot
-  o += 4u * (uint32_t)CI;
+  L.resid = o;                                         // u = H e, 16 bits per lane: bit k = check item k
+  o += 2u * 64u;
   o = lds_align16(o);
   L.chk = o;                                           // checks of every bit (u16)
   o += 2u * (uint32_t)(N * DV);
@@ -79,8 +83,8 @@ __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int W, int CI, i
   o += 4u * (uint32_t)(ring * META);
   L.ring_tb = o;                                       // trial bits of every lane of an entry
   o += 4u * (uint32_t)(ring * (64 / D));
-  L.ring_syn = o;                                      // syndrome bits of every lane of an entry
-  o += 4u * (uint32_t)(ring * (64 / D));
+  L.ring_syn = o;                                      // syndrome bits of every lane of an entry (u16)
+  o += 2u * (uint32_t)(ring * (64 / D));
   o = lds_align16(o);
   // layered schedule: the posterior of every bit of every slot, and the bit
   // of every (check, position)
