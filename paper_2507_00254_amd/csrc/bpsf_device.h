@@ -62,6 +62,12 @@ __device__ __forceinline__ long long bcast0ll(long long x) {
   return ((long long)hi << 32) | (unsigned int)lo;
 }
 
+// a ^ b ^ c in one instruction (v_bitop3, truth table 0x96)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Butterfly reductions over the G contiguous lanes of a slot (G a power of
 // two, the same in every lane). Steps inside a row of 16 lanes use DPP lane
 // permutations (no LDS traffic).

@@ -420,14 +420,16 @@ __device__ __forceinline__ void decode_code(const Args& a, bool own_first)
           }
           Real m1 = R::minr(R::absr(x[0]), R::absr(x[1]));
           Real m2 = R::maxr(R::absr(x[0]), R::absr(x[1]));
-          uint32_t P = R::sw(x[0]) ^ R::sw(x[1]);
 #pragma unroll
           for (int j = 2; j < W; ++j) {
             m2 = R::med3(m1, m2, R::absr(x[j]));
             m1 = R::minr(m1, R::absr(x[j]));
-            P ^= R::sw(x[j]);
           }
-          P ^= (synbits >> k) << 31;                      // (-1)^{s_c}
+          // sign parity, (-1)^{s_c} included, in bit 31; two signs per op
+          uint32_t P = (synbits >> k) << 31;
+#pragma unroll
+          for (int j = 0; j + 1 < W; j += 2) P = xor3(P, R::sw(x[j]), R::sw(x[j + 1]));
+          if constexpr (W % 2 != 0) P ^= R::sw(x[W - 1]);
           Real s1 = R::flip(alpha * m1, P), s2 = R::flip(alpha * m2, P);
           R::opaque(s1);
           R::opaque(s2);
@@ -471,14 +473,16 @@ __device__ __forceinline__ void decode_code(const Args& a, bool own_first)
           }
           Real m1 = R::minr(R::absr(xc[0]), R::absr(xc[1]));
           Real m2 = R::maxr(R::absr(xc[0]), R::absr(xc[1]));
-          uint32_t P = R::sw(xc[0]) ^ R::sw(xc[1]);
 #pragma unroll
           for (int j = 2; j < W; ++j) {
             m2 = R::med3(m1, m2, R::absr(xc[j]));
             m1 = R::minr(m1, R::absr(xc[j]));
-            P ^= R::sw(xc[j]);
           }
-          P ^= synbits << (31 - k);                         // (-1)^{s_c}
+          // sign parity, (-1)^{s_c} included, in bit 31; two signs per op
+          uint32_t P = synbits << (31 - k);
+#pragma unroll
+          for (int j = 0; j + 1 < W; j += 2) P = xor3(P, R::sw(xc[j]), R::sw(xc[j + 1]));
+          if constexpr (W % 2 != 0) P ^= R::sw(xc[W - 1]);
           Real s1 = R::flip(alpha * m1, P), s2 = R::flip(alpha * m2, P);
           R::opaque(s1);
           R::opaque(s2);
