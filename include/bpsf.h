@@ -248,11 +248,17 @@ int bpsf_mix_last_stats(bpsf_mix mix, void* stream, bpsf_stats* per_code, int64_
 /*
  * Launch shape. A decode kernel runs D decodes per wavefront ("decodes per
  * wave", a power of two; 64 / D lanes per decode) in a persistent grid of
- * W waves per compute unit. Results do not depend on either.
+ * W waves per compute unit. Results do not depend on either, nor on the
+ * kernel family: row-weight-6 codes have a large family and a small one
+ * with a third of the checks and bits per lane. A bpsf_decode call of at
+ * most 4096 shots, or any call once D is fixed, runs the family with the
+ * fewest items per lane that fits (at D); a larger call runs the large
+ * family at its largest D (small calls leave the GPU mostly idle, so one
+ * iteration of one wave is their latency).
  * bpsf_tile_options writes the D values the code fits, most first, to host
  * d_out (up to cap) and returns their number. bpsf_set_tile fixes D and W
- * for later calls on the handle (0 = default: the largest D that fits, as
- * many waves as fit). bpsf_autotune times bpsf_decode on a sample (device
+ * for later calls on the handle (0 = default: as above, as many waves as
+ * fit). bpsf_autotune times bpsf_decode on a sample (device
  * syndromes [shots][M], host priors, as for bpsf_decode; best of `reps`
  * calls after one untimed call) for every D and a range of W, keeps the
  * fastest on the handle and describes it in *out (host). It allocates and

@@ -132,10 +132,47 @@ bool tile_fits(const bpsf_code_s* c, int fam, int D)
   return c->M <= G * f.IC && c->N <= G * f.IV && c->N * f.DV <= 65535;
 }
 
-// Default tile: a family the code fits, at the most decodes per wave (the
-// handle's tuned or forced D when set).
-int pick_tile(const bpsf_code_s* c, TileDesc* out)
+// Shots up to which a single-code call takes the family with the fewest
+// items per lane: such calls do not fill the GPU with the large families, so
+// their time is the iterations of one decode, and one iteration of a wave is
+// about three times shorter with a third of the items.
+constexpr int64_t SMALL_CALL_SHOTS = 4096;
+
+// Edges a lane of family `fam` works on per iteration.
+int family_items(int fam)
 {
+  const FamilyDesc f = family_desc(fam);
+  return f.IC * f.W + f.IV * f.DV;
+}
+
+// Tile of a single-code call of `shots` shots (a forced D takes the family
+// with the fewest items per lane that fits at D; a small call that family at
+// its most decodes per wave), or, for shots < 0 (mixed calls, traces), the
+// default tile: the first family the code fits, at the most decodes per wave
+// (the handle's tuned or forced D when set).
+int pick_tile(const bpsf_code_s* c, TileDesc* out, int64_t shots = -1)
+{
+  if (shots >= 0 && (c->tuned_D > 0 || shots <= SMALL_CALL_SHOTS)) {
+    int best = -1, best_D = 0;
+    for (int fam = 0; fam < family_count(); ++fam) {
+      int D = 0;
+      if (c->tuned_D > 0) {
+        if (tile_fits(c, fam, c->tuned_D)) D = c->tuned_D;
+      } else {
+        for (int d = MAX_D; d >= 1 && !D; d >>= 1)
+          if (tile_fits(c, fam, d)) D = d;
+      }
+      if (D && (best < 0 || family_items(fam) < family_items(best))) {
+        best = fam;
+        best_D = D;
+      }
+    }
+    if (best >= 0) {
+      *out = TileDesc{best, best_D};
+      return 0;
+    }
+    return -1;
+  }
   for (int fam = 0; fam < family_count(); ++fam) {
     if (c->tuned_D > 0 && tile_fits(c, fam, c->tuned_D)) {
       *out = TileDesc{fam, c->tuned_D};
@@ -380,7 +417,7 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
   pl->wide = c->wide;
   pl->sparse = c->sparse;
   if (c->wide >= 0 || c->sparse >= 0) pl->tile = TileDesc{-1, 1};
-  else if (pick_tile(c, &pl->tile)) return fail(BPSF_ENOTSUP, "no kernel tile for this code");
+  else if (pick_tile(c, &pl->tile, shots)) return fail(BPSF_ENOTSUP, "no kernel tile for this code");
   const TileDesc& t = pl->tile;
   Args& a = pl->args;
   int rc = fill_code_args(c, p, t, &a);
@@ -1096,12 +1133,14 @@ int bpsf_tile_options(bpsf_code c, int32_t* d_out, int32_t cap)
 {
   if (!c) return fail(BPSF_EINVAL, "code is NULL");
   int n = 0;
-  for (int fam = 0; fam < family_count(); ++fam)
-    for (int D = MAX_D; D >= 1; D >>= 1)
-      if (tile_fits(c, fam, D)) {
-        if (d_out && n < cap) d_out[n] = D;
-        ++n;
-      }
+  for (int D = MAX_D; D >= 1; D >>= 1) {
+    bool fits = false;
+    for (int fam = 0; fam < family_count() && !fits; ++fam) fits = tile_fits(c, fam, D);
+    if (fits) {
+      if (d_out && n < cap) d_out[n] = D;
+      ++n;
+    }
+  }
   return n;
 }
 

@@ -14,9 +14,11 @@ namespace bpsf {
 // fits when M <= G * IC and N <= G * IV.
 //
 // Messages of slot d sit at stride MS = G * IC inside each edge position of
-// CI = 64 * IC entries. With IC = 1 (mod 8), MS = G (mod 32) for every G >= 4,
-// so the 32 lanes of each half-wave hit 32 distinct banks in the check phase,
-// and CI does not depend on D.
+// CI = 64 * IC entries, so CI does not depend on D. A lane's check items sit
+// at IC * lane + k: with IC odd the 32 lanes of a half-wave hit 32 distinct
+// banks in the check phase. With IC = 1 (mod 8) also MS = G (mod 32) for
+// every G >= 4, which keeps the bit-phase gathers of the slots sharing a
+// half-wave apart; the small family (IC = 3) runs at G >= 16.
 // ints per ring entry header: shot (two words for the first BP), record,
 // trial, first-BP iterations
 constexpr int RING_META = 5;
@@ -28,17 +30,20 @@ struct Family {
   static constexpr int PL = 8;         // bit planes of flip_count
   static constexpr int META = RING_META;
   static constexpr int KMAX = 16;      // largest |Phi|
-  static_assert(IC % 8 == 1, "IC = 1 (mod 8) keeps check-phase accesses free of bank conflicts");
+  static_assert(IC % 2 == 1, "IC odd keeps check-phase accesses free of bank conflicts");
   static_assert(IC <= 16 && IV <= 32, "items per lane must fit the 16-bit column masks and 32-bit bit masks");
   static_assert(W >= 2 && DV >= 1, "row weight >= 2");
 };
 
 // Compiled families (IC, IV, W, DV): row weight 6 / column weight 3 (the
 // bivariate-bicycle and coprime-BB codes), row weight 10 / column weight 5
-// (the generalized-bicycle code of Appendix A).
+// (the generalized-bicycle code of Appendix A), and a small row-weight-6
+// family with a third of the items per lane, for calls too small to fill the
+// GPU, where the time of one iteration of one wave is the latency.
 #define BPSF_FAMILY_LIST(X) \
   X(9, 18, 6, 3)            \
-  X(9, 9, 10, 5)
+  X(9, 9, 10, 5)            \
+  X(3, 5, 6, 3)
 
 constexpr int MAX_D = 16;
 
