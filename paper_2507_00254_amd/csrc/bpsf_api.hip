@@ -987,10 +987,21 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
   ma.n_codes = m->n;
   size_t lds = 0;
   int stride = 0;
+  // grouped shots of a single code run that code's own kernels (the same
+  // decode body, arguments in registers), with the tile a single-code call of
+  // as many shots would take
+  int only = -1;
+  if (counts)
+    for (int i = 0; i < m->n; ++i)
+      if (counts[i] > 0) only = only == -1 ? i : -2;
   TileDesc tiles[MIX_MAX_CODES];
   for (int i = 0; i < m->n; ++i) {
     bpsf_code_s* c = m->codes[i];
-    if (pick_tile(c, &tiles[i]) || tiles[i].fam != m->fam) return fail(BPSF_ENOTSUP, "code %d changed kernel family", i);
+    if (i == only) {
+      if (pick_tile(c, &tiles[i], counts[i])) return fail(BPSF_ENOTSUP, "code %d has no kernel tile", i);
+    } else if (pick_tile(c, &tiles[i]) || tiles[i].fam != m->fam) {
+      return fail(BPSF_ENOTSUP, "code %d changed kernel family", i);
+    }
     if ((rc = fill_code_args(c, p, tiles[i], &ma.code[i]))) return rc;
     // a mixed launch runs the uniform-LLR kernel only when every code qualifies
     lds = std::max(lds, tile_lds(c, tiles[i], fp64, uniform));
@@ -1040,12 +1051,6 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
   b.lists = static_cast<int32_t*>(m->lists.p);
   for (int i = 0; i < m->n; ++i) b.counts[i] = mixw + MIX_TASKS + i;
   b.bad = mixw + MIX_BAD;
-  // grouped shots of a single code: that code's own kernels (the same decode
-  // body), which keep their arguments in registers
-  int only = -1;
-  if (counts)
-    for (int i = 0; i < m->n; ++i)
-      if (counts[i] > 0) only = only == -1 ? i : -2;
   if (only >= 0) {
     bpsf_code_s* c = m->codes[only];
     const Args& a = ma.code[only];
@@ -1055,7 +1060,11 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
       int per_cu = 0;
       if (occupancy(false, tiles[only], fp64, c->uniform, mode, l1, &a, nullptr, &per_cu))
         return fail(BPSF_EDEVICE, "occupancy query failed for mode %d", mode);
-      if (tile_dispatch(0, tiles[only], fp64, c->uniform, mode, false, a, l1, per_cu * c->cus, stream, nullptr))
+      // no more waves than the phase can have chunks of tasks
+      const long long most = mode == MODE_CAND ? a.shots * (long long)a.n_trials : a.shots;
+      const long long chunks = (most + a.chunk - 1) / a.chunk;
+      const int grid = chunks < per_cu * c->cus ? (int)std::max(1LL, chunks) : per_cu * c->cus;
+      if (tile_dispatch(0, tiles[only], fp64, c->uniform, mode, false, a, l1, grid, stream, nullptr))
         return fail(BPSF_EDEVICE, "launch of phase %d failed", mode);
     }
     return 0;
@@ -1243,7 +1252,10 @@ int bpsf_reserve(bpsf_code c, int64_t shots, const bpsf_params* p)
   if (shots < 1 || shots > 0x7fffffffLL) return fail(BPSF_EINVAL, "shots must be in 1..2^31-1");
   std::lock_guard<std::mutex> lk(c->mu);
   Plan pl;
-  return make_plan(c, p, shots, &pl);
+  // the tile of a call of `shots`, and that of a small call (more record
+  // words per shot)
+  if ((rc = make_plan(c, p, shots, &pl))) return rc;
+  return make_plan(c, p, std::min(shots, SMALL_CALL_SHOTS), &pl);
 }
 
 int bpsf_mix_reserve(bpsf_mix m, int64_t shots, const bpsf_params* p)
@@ -1256,11 +1268,14 @@ int bpsf_mix_reserve(bpsf_mix m, int64_t shots, const bpsf_params* p)
   std::lock_guard<std::mutex> lk(m->mu);
   int stride = 0;
   for (int i = 0; i < m->n; ++i) {
-    TileDesc t;
-    Args a;
-    if (pick_tile(m->codes[i], &t)) return fail(BPSF_ENOTSUP, "code %d has no kernel tile", i);
-    if ((rc = fill_code_args(m->codes[i], p, t, &a))) return rc;
-    stride = std::max(stride, a.rec_stride);
+    // the mixed tile, and the tile of a small batch of this code alone
+    for (int64_t call : {(int64_t)-1, std::min(shots, SMALL_CALL_SHOTS)}) {
+      TileDesc t;
+      Args a;
+      if (pick_tile(m->codes[i], &t, call)) return fail(BPSF_ENOTSUP, "code %d has no kernel tile", i);
+      if ((rc = fill_code_args(m->codes[i], p, t, &a))) return rc;
+      stride = std::max(stride, a.rec_stride);
+    }
   }
   const size_t n = (size_t)shots;
   if (m->lists.ensure(sizeof(int32_t) * n * m->n) || m->rec_lists.ensure(sizeof(int32_t) * n * m->n) ||
