@@ -300,7 +300,7 @@ def run_dem(args):
     n_s = 5 sampled trials per weight 1..6 (30 trials of 100 iterations),
     first success kept with pruning; float messages (sparse kernel family).
     A fourth point runs p = 0.003 with |Phi| = 50 and n_s = 10 per weight
-    1..10 (100 trials)."""
+    1..10 (100 trials). Each point also times single-syndrome calls."""
     import torch
 
     from paper_2507_00254_amd import bpsf as B
@@ -339,12 +339,27 @@ def run_dem(args):
         res = (corr.cpu().numpy() ^ err).astype(np.int64)
         fail = ((res @ dem.obs.T.astype(np.int64)) & 1).any(axis=1) | (conv.cpu().numpy() == 0)
         ler = float(fail.mean())
+        # per-syndrome latency: one syndrome per call on an idle GPU (GPU
+        # events around the call), the first args.dem_latency_calls shots
+        lat = []
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for i in range(min(args.dem_latency_calls, n)):
+            ev0.record(stream)
+            B.bpsf_decode(handle, s[i:i + 1], dem.priors, prm if phi == 16 else prm50, corr[i:i + 1], conv[i:i + 1],
+                          it[i:i + 1], stream)
+            ev1.record(stream)
+            ev1.synchronize()
+            lat.append(ev0.elapsed_time(ev1) * 1e3)
+        lat = np.array(lat) if lat else np.array([np.nan])
         rows.append({"p": p, "phi": phi, "trials": int(len(masks) if phi == 16 else len(masks50)),
                      "shots": n, "mechanisms": int(dem.h.shape[1]), "edges": edges,
                      "ms_per_step": ms, "value": n / (ms * 1e-3), "phases_ms": avg,
                      "mean_latency_iterations": float(it.float().mean().item()),
                      "work": {**iters, "failed_shots": st["failed_shots"], "errors": st["errors"]},
                      "ler": ler, "ler_per_round": 1.0 - (1.0 - ler) ** (1.0 / 12),
+                     "syndrome_latency_us": {"calls": int(len(lat)), "mean": float(lat.mean()),
+                                             "p50": float(np.percentile(lat, 50)),
+                                             "p99": float(np.percentile(lat, 99)), "max": float(lat.max())},
                      "roofline": {"bound": "lds", "kernel": dom, "achieved": ach, "peak": LDS_PEAK_GBS,
                                   "unit": "GB/s", "frac": ach / LDS_PEAK_GBS,
                                   "per_unit": f"{EDGE_BYTES} B per edge-iteration x {edges} edges x {iters[dom]} "
@@ -471,6 +486,8 @@ def main():
                          "phen: phenomenological [[144]] over 12 rounds; dem: circuit-level detector error "
                          "model of [[144]] over 12 rounds; layered: flooding vs layered BP")
     ap.add_argument("--dem-shots", type=int, default=20_000, help="dem: shots per error rate")
+    ap.add_argument("--dem-latency-calls", type=int, default=300,
+                    help="dem: single-syndrome calls timed per error rate")
     ap.add_argument("--loads", type=str, default="1e4,3e4,1e5,3e5,1e6,3e6,1e7",
                     help="serve: offered loads in shots/s")
     ap.add_argument("--lanes", type=int, default=2, help="serve: streams of the batched server")

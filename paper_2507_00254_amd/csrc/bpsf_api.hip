@@ -791,11 +791,13 @@ int bpsf_decode(bpsf_code c, const uint8_t* syndromes, const double* priors, int
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (reset_counters(a.counters, CNT_WORDS, stream)) return fail(BPSF_EDEVICE, "counter reset launch");
   auto launch = [&](int mode) {
-    if (pl.sparse >= 0) return sparse_dispatch(0, pl.sparse, mode, a, pl.lds, pl.grid[mode], stream, nullptr);
-    if (pl.wide >= 0) return wide_dispatch(0, pl.wide, fp64, mode, a, pl.lds, pl.grid[mode], stream, nullptr);
-    // no more waves than the phase can have chunks of tasks: every shot (a
-    // first BP or a re-run) or every trial of every shot
+    // no more workgroups than the phase can have tasks (one decode per
+    // workgroup) or chunks of tasks (one-wave kernels): every shot (a first
+    // BP or a re-run) or every trial of every shot
     const long long most = mode == MODE_CAND ? shots * (long long)a.n_trials : shots;
+    const int groups = most < pl.grid[mode] ? (int)std::max(1LL, most) : pl.grid[mode];
+    if (pl.sparse >= 0) return sparse_dispatch(0, pl.sparse, mode, a, pl.lds, groups, stream, nullptr);
+    if (pl.wide >= 0) return wide_dispatch(0, pl.wide, fp64, mode, a, pl.lds, groups, stream, nullptr);
     const long long chunks = (most + a.chunk - 1) / a.chunk;
     const int grid = chunks < pl.grid[mode] ? (int)std::max(1LL, chunks) : pl.grid[mode];
     return tile_dispatch(0, pl.tile, fp64, c->uniform, mode, false, a, pl.lds, grid, stream, nullptr,

@@ -111,6 +111,25 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
   const bool adaptive = !(a.alpha > 0.0);
   const float alpha_fixed = adaptive ? 1.0f : (float)a.alpha;
 
+  // ---- task source ----------------------------------------------------------
+  long long n_tasks;
+  unsigned long long* next_ctr;
+  if constexpr (MODE == MODE_MAIN) {
+    n_tasks = a.shots;
+    next_ctr = &a.counters[CNT_MAIN_NEXT];
+  } else if constexpr (MODE == MODE_CAND) {
+    n_tasks = (long long)__atomic_load_n(&a.counters[CNT_FAILED], __ATOMIC_RELAXED) * a.n_trials;
+    next_ctr = &a.counters[CNT_CAND_NEXT];
+  } else {
+    n_tasks = (long long)__atomic_load_n(&a.counters[CNT_FAILED], __ATOMIC_RELAXED);
+    next_ctr = &a.counters[CNT_EMIT_NEXT];
+  }
+  // the workgroup's first task is its block index and the counter hands out
+  // the rest after gridDim.x, so a workgroup with nothing to do leaves before
+  // its set-up (small calls launch many)
+  if ((long long)blockIdx.x >= n_tasks) return;
+  bool first_task = true;
+
   // ---- per-thread constants -------------------------------------------------
   // my checks: their edges as packed 16-bit cell indices (my pad cell past
   // the weight), and the wave's largest weight
@@ -157,19 +176,6 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
   // cells past the last column: read by the bit phase, never used
   for (int i = g; i < DVMAX; i += T) msg[E + i] = 0.f;
 
-  // ---- task source ----------------------------------------------------------
-  long long n_tasks;
-  unsigned long long* next_ctr;
-  if constexpr (MODE == MODE_MAIN) {
-    n_tasks = a.shots;
-    next_ctr = &a.counters[CNT_MAIN_NEXT];
-  } else if constexpr (MODE == MODE_CAND) {
-    n_tasks = (long long)__atomic_load_n(&a.counters[CNT_FAILED], __ATOMIC_RELAXED) * a.n_trials;
-    next_ctr = &a.counters[CNT_CAND_NEXT];
-  } else {
-    n_tasks = (long long)__atomic_load_n(&a.counters[CNT_FAILED], __ATOMIC_RELAXED);
-    next_ctr = &a.counters[CNT_EMIT_NEXT];
-  }
   const int rstride = a.rec_stride;
   unsigned long long st_iters = 0, st_conv = 0, st_err = 0;
 
@@ -177,7 +183,8 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
     // ---- claim one task for the workgroup (thread 0 decides for everyone) ----
     __syncthreads();
     if (g == 0) {
-      const long long t0 = (long long)atomicAdd(next_ctr, 1ull);
+      const long long t0 = first_task ? (long long)blockIdx.x
+                                      : (long long)atomicAdd(next_ctr, 1ull) + (long long)gridDim.x;
       long long f = 0, ti = 0;
       int skip = 0;
       if (MODE != MODE_MAIN && t0 < n_tasks) {
@@ -201,6 +208,7 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
       task[3] = skip;
     }
     __syncthreads();
+    first_task = false;
     const long long t = task[0];
     if (t >= n_tasks) break;
     if (task[3]) continue;

@@ -50,6 +50,25 @@ __device__ __forceinline__ void decode_wide(const Args& a)
   const Real alpha_fixed = R::from_double(adaptive ? 1.0 : a.alpha);
   const Real INF = (Real)INFINITY;
 
+  // ---- task source ----------------------------------------------------------
+  long long n_tasks;
+  unsigned long long* next_ctr;
+  if constexpr (MODE == MODE_MAIN) {
+    n_tasks = a.task_count ? (long long)__atomic_load_n(a.task_count, __ATOMIC_RELAXED) : a.shots;
+    next_ctr = &a.counters[CNT_MAIN_NEXT];
+  } else if constexpr (MODE == MODE_CAND) {
+    n_tasks = (long long)__atomic_load_n(&a.counters[CNT_FAILED], __ATOMIC_RELAXED) * a.n_trials;
+    next_ctr = &a.counters[CNT_CAND_NEXT];
+  } else {
+    n_tasks = (long long)__atomic_load_n(&a.counters[CNT_FAILED], __ATOMIC_RELAXED);
+    next_ctr = &a.counters[CNT_EMIT_NEXT];
+  }
+  // the workgroup's first task is its block index and the counter hands out
+  // the rest after gridDim.x, so a workgroup with nothing to do leaves before
+  // its set-up (small calls launch many)
+  if ((long long)blockIdx.x >= n_tasks) return;
+  bool first_task = true;
+
   // ---- per-lane constants ---------------------------------------------------
   const uint32_t zero_cell = lay.zero;
   const uint32_t dummy_cell = lay.dummy + (uint32_t)sizeof(Real) * (uint32_t)g;   // write-only
@@ -86,19 +105,6 @@ __device__ __forceinline__ void decode_wide(const Args& a)
   for (int i = g; i < MP; i += G) uw[i] = 0u;
   if (g == 0) *reinterpret_cast<Real*>(smem + zero_cell) = (Real)0;
 
-  // ---- task source ----------------------------------------------------------
-  long long n_tasks;
-  unsigned long long* next_ctr;
-  if constexpr (MODE == MODE_MAIN) {
-    n_tasks = a.task_count ? (long long)__atomic_load_n(a.task_count, __ATOMIC_RELAXED) : a.shots;
-    next_ctr = &a.counters[CNT_MAIN_NEXT];
-  } else if constexpr (MODE == MODE_CAND) {
-    n_tasks = (long long)__atomic_load_n(&a.counters[CNT_FAILED], __ATOMIC_RELAXED) * a.n_trials;
-    next_ctr = &a.counters[CNT_CAND_NEXT];
-  } else {
-    n_tasks = (long long)__atomic_load_n(&a.counters[CNT_FAILED], __ATOMIC_RELAXED);
-    next_ctr = &a.counters[CNT_EMIT_NEXT];
-  }
   const int rstride = a.rec_stride;
 
   uint32_t prevt = 0;                 // hard decisions u was last toggled to
@@ -111,7 +117,8 @@ __device__ __forceinline__ void decode_wide(const Args& a)
     // updates and split the workgroup's barriers)
     __syncthreads();
     if (g == 0) {
-      const long long t0 = (long long)atomicAdd(next_ctr, 1ull);
+      const long long t0 = first_task ? (long long)blockIdx.x
+                                      : (long long)atomicAdd(next_ctr, 1ull) + (long long)gridDim.x;
       long long f = 0, ti = 0;
       unsigned long long kk = KEY_NONE;
       int skip = 0;
@@ -137,6 +144,7 @@ __device__ __forceinline__ void decode_wide(const Args& a)
       task[3] = skip;
     }
     __syncthreads();
+    first_task = false;
     const long long t = task[0];
     if (t >= n_tasks) break;
     if (task[3]) continue;
