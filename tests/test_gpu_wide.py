@@ -94,3 +94,22 @@ def test_wide_codes_do_not_mix_and_have_no_tiles():
     finally:
         B.bpsf_free_code(hw)
         B.bpsf_free_code(hb)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7])
+def test_ragged_calls_alone_equal_the_batch(n):
+    """Calls of a few shots (fewer workgroups than the grid holds; the first
+    task of a workgroup is its block index) give each shot the result it gets
+    in a batch, and the oracle's. Failing shots are included (p = 0.03)."""
+    h = _phen("bb72", 4)
+    p = 0.03
+    syn = _inputs(h, p, 40, 2)
+    prm = U.oracle_params(max_iter=60, cand_max_iter=15, k=6)
+    full = U.gpu_decode(h, syn, p, prm)
+    assert full["stats"]["failed_shots"] > 0
+    for i in range(0, 40 - n + 1, 9):
+        part = U.gpu_decode(h, syn[i:i + n], p, prm)
+        for f in ("correction", "converged", "iterations"):
+            assert np.array_equal(part[f], full[f][i:i + n]), (n, i, f)
+    o = U.oracle_decode(h, syn, p, prm, precision="f32")
+    assert len(U.mismatches(full, o)) == 0
