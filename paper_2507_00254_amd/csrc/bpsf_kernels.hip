@@ -556,11 +556,14 @@ __device__ __forceinline__ void decode_code(const Args& a, bool own_first)
         const int k = __builtin_ctz(f);
         f &= f - 1u;
         const int v = q + (k << LG);
+        // the bit's checks are all read before the first toggle (a toggle
+        // could alias a later read as far as the compiler knows, which would
+        // serialize every read behind the previous toggle)
+        uint32_t t[DV];
 #pragma unroll
-        for (int i = 0; i < DV; ++i) {
-          const uint32_t t = chk[v * DV + i];
-          atomicXor(&uw[ubase + (t >> 5)], 1u << (t & 31u));
-        }
+        for (int i = 0; i < DV; ++i) t[i] = chk[v * DV + i];
+#pragma unroll
+        for (int i = 0; i < DV; ++i) atomicXor(&uw[ubase + (t[i] >> 5)], 1u << (t[i] & 31u));
       }
     }
     __syncthreads();
