@@ -274,11 +274,13 @@ __device__ __forceinline__ void decode_wide(const Args& a)
           const int k = __builtin_ctz(fl);
           fl &= fl - 1u;
           const int v = g + G * k;
+          // all the bit's checks are loaded before the first toggle
+          int cs[DV];
 #pragma unroll
-          for (int j = 0; j < DV; ++j) {
-            const int c = a.var_chk[v * DV + j];
-            if (c != 0xffff) atomicXor(&uw[c], 1u);
-          }
+          for (int j = 0; j < DV; ++j) cs[j] = a.var_chk[v * DV + j];
+#pragma unroll
+          for (int j = 0; j < DV; ++j)
+            if (cs[j] != 0xffff) atomicXor(&uw[cs[j]], 1u);
         }
       }
       __syncthreads();
