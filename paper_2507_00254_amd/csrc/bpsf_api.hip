@@ -132,11 +132,14 @@ bool tile_fits(const bpsf_code_s* c, int fam, int D)
   return c->M <= G * f.IC && c->N <= G * f.IV && c->N * f.DV <= 65535;
 }
 
-// Shots up to which a single-code call takes the family with the fewest
-// items per lane: such calls do not fill the GPU with the large families, so
-// their time is the iterations of one decode, and one iteration of a wave is
-// about three times shorter with a third of the items.
-constexpr int64_t SMALL_CALL_SHOTS = 4096;
+// A call takes the family with the fewest items per lane, at its most
+// decodes per wave D, when it has at most SMALL_CALL_SHOTS_PER_D * D shots:
+// such calls do not fill the GPU, so their time is the iterations of one
+// decode, and one iteration of a wave is about twice as fast with a third of
+// the items. Measured on [[144]] (D = 2 there) the small family is faster up
+// to about 16k shots, on [[288]] (D = 1) up to about 3k.
+constexpr int64_t SMALL_CALL_SHOTS_PER_D = 2048;
+constexpr int64_t SMALL_CALL_SHOTS = SMALL_CALL_SHOTS_PER_D * MAX_D;   // the most any code can use
 
 // Edges a lane of family `fam` works on per iteration.
 int family_items(int fam)
@@ -152,7 +155,7 @@ int family_items(int fam)
 // (the handle's tuned or forced D when set).
 int pick_tile(const bpsf_code_s* c, TileDesc* out, int64_t shots = -1)
 {
-  if (shots >= 0 && (c->tuned_D > 0 || shots <= SMALL_CALL_SHOTS)) {
+  if (shots >= 0) {
     int best = -1, best_D = 0;
     for (int fam = 0; fam < family_count(); ++fam) {
       int D = 0;
@@ -167,11 +170,11 @@ int pick_tile(const bpsf_code_s* c, TileDesc* out, int64_t shots = -1)
         best_D = D;
       }
     }
-    if (best >= 0) {
+    if (best < 0) return -1;
+    if (c->tuned_D > 0 || shots <= SMALL_CALL_SHOTS_PER_D * best_D) {
       *out = TileDesc{best, best_D};
       return 0;
     }
-    return -1;
   }
   for (int fam = 0; fam < family_count(); ++fam) {
     if (c->tuned_D > 0 && tile_fits(c, fam, c->tuned_D)) {
@@ -996,11 +999,27 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
   if (counts)
     for (int i = 0; i < m->n; ++i)
       if (counts[i] > 0) only = only == -1 ? i : -2;
+  // a small mixed call runs the tiles single-code calls of its size would
+  // take when they share a family (the small family, for codes it fits)
+  int fam = m->fam;
+  bool small = only < 0 && shots <= SMALL_CALL_SHOTS;
+  for (int i = 0, f0 = -1; i < m->n && small; ++i) {
+    TileDesc t;
+    if (pick_tile(m->codes[i], &t, shots) || (f0 >= 0 && t.fam != f0)) {
+      small = false;
+    } else {
+      f0 = t.fam;
+      fam = t.fam;
+    }
+  }
+  if (!small) fam = m->fam;
   TileDesc tiles[MIX_MAX_CODES];
   for (int i = 0; i < m->n; ++i) {
     bpsf_code_s* c = m->codes[i];
     if (i == only) {
       if (pick_tile(c, &tiles[i], counts[i])) return fail(BPSF_ENOTSUP, "code %d has no kernel tile", i);
+    } else if (small) {
+      if (pick_tile(c, &tiles[i], shots)) return fail(BPSF_ENOTSUP, "code %d has no kernel tile", i);
     } else if (pick_tile(c, &tiles[i]) || tiles[i].fam != m->fam) {
       return fail(BPSF_ENOTSUP, "code %d changed kernel family", i);
     }
@@ -1074,18 +1093,18 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
   int grid[3];
   for (int mode = 0; mode < 3; ++mode) {
     int per_cu = 0;
-    if (occupancy(true, TileDesc{m->fam, 0}, fp64, uniform, mode, lds, nullptr, &ma, &per_cu))
+    if (occupancy(true, TileDesc{fam, 0}, fp64, uniform, mode, lds, nullptr, &ma, &per_cu))
       return fail(BPSF_EDEVICE, "occupancy query failed for mode %d", mode);
     grid[mode] = per_cu * m->codes[0]->cus;
   }
   if (reset_counters(cnt, (int)words, stream)) return fail(BPSF_EDEVICE, "counter reset launch");
   if (!counts && bucket_launch(b, stream)) return fail(BPSF_EDEVICE, "bucketing launch failed");
-  if (mixed_dispatch(0, m->fam, fp64, uniform, MODE_MAIN, ma, lds, grid[MODE_MAIN], stream, nullptr))
+  if (mixed_dispatch(0, fam, fp64, uniform, MODE_MAIN, ma, lds, grid[MODE_MAIN], stream, nullptr))
     return fail(BPSF_EDEVICE, "first-BP launch failed");
   if (p->k > 0) {
-    if (mixed_dispatch(0, m->fam, fp64, uniform, MODE_CAND, ma, lds, grid[MODE_CAND], stream, nullptr))
+    if (mixed_dispatch(0, fam, fp64, uniform, MODE_CAND, ma, lds, grid[MODE_CAND], stream, nullptr))
       return fail(BPSF_EDEVICE, "trial launch failed");
-    if (mixed_dispatch(0, m->fam, fp64, uniform, MODE_EMIT, ma, lds, grid[MODE_EMIT], stream, nullptr))
+    if (mixed_dispatch(0, fam, fp64, uniform, MODE_EMIT, ma, lds, grid[MODE_EMIT], stream, nullptr))
       return fail(BPSF_EDEVICE, "re-run launch failed");
   }
   return 0;
@@ -1254,10 +1273,11 @@ int bpsf_reserve(bpsf_code c, int64_t shots, const bpsf_params* p)
   if (shots < 1 || shots > 0x7fffffffLL) return fail(BPSF_EINVAL, "shots must be in 1..2^31-1");
   std::lock_guard<std::mutex> lk(c->mu);
   Plan pl;
-  // the tile of a call of `shots`, and that of a small call (more record
-  // words per shot)
+  // the tile of a call of `shots`, and those of the largest calls that take
+  // the small family (more record words per shot)
   if ((rc = make_plan(c, p, shots, &pl))) return rc;
-  return make_plan(c, p, std::min(shots, SMALL_CALL_SHOTS), &pl);
+  for (int D = 1; D <= MAX_D && !rc; D *= 2) rc = make_plan(c, p, std::min(shots, SMALL_CALL_SHOTS_PER_D * D), &pl);
+  return rc;
 }
 
 int bpsf_mix_reserve(bpsf_mix m, int64_t shots, const bpsf_params* p)
@@ -1271,7 +1291,7 @@ int bpsf_mix_reserve(bpsf_mix m, int64_t shots, const bpsf_params* p)
   int stride = 0;
   for (int i = 0; i < m->n; ++i) {
     // the mixed tile, and the tile of a small batch of this code alone
-    for (int64_t call : {(int64_t)-1, std::min(shots, SMALL_CALL_SHOTS)}) {
+    for (int64_t call : {(int64_t)-1, std::min(shots, SMALL_CALL_SHOTS_PER_D), std::min(shots, SMALL_CALL_SHOTS)}) {
       TileDesc t;
       Args a;
       if (pick_tile(m->codes[i], &t, call)) return fail(BPSF_ENOTSUP, "code %d has no kernel tile", i);

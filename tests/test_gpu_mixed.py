@@ -45,9 +45,10 @@ def _per_code(out, shot_code, c, n_bits):
             "iterations": out["iterations"][sel]}, sel
 
 
-@pytest.mark.parametrize("precision", ["f32", "f64"])
-def test_mixed_five_codes_match_single_calls_and_oracle(precision):
-    p, per = 0.05, 500
+# 2500 shots run the small family's tiles, 5000 the large families'
+@pytest.mark.parametrize("precision,per", [("f32", 500), ("f64", 500), ("f32", 1000)])
+def test_mixed_five_codes_match_single_calls_and_oracle(precision, per):
+    p = 0.05
     hs = [codes.get_code(n).hx for n in NAMES]
     sc, syn, _, _ = shots.mixed_batch(hs, p, per, shots.stream_key(shots.MASTER_SEED, 900))
     prm = U.oracle_params(k=6)
