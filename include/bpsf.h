@@ -251,12 +251,13 @@ int bpsf_mix_last_stats(bpsf_mix mix, void* stream, bpsf_stats* per_code, int64_
  * W waves per compute unit. Results do not depend on either, nor on the
  * kernel family: row-weight-6 codes have a large family and a small one
  * with a third of the checks and bits per lane. A bpsf_decode call of at
- * most 2048 x D shots, D being the small family's largest decodes per wave
- * for the code (4096 shots for [[144,12,12]]), or any call once D is fixed,
+ * most 4096 x D shots, D being the small family's largest decodes per wave
+ * for the code (8192 shots for [[144,12,12]]), or any call once D is fixed,
  * runs the family with the fewest items per lane that fits (at D); a larger
  * call runs the large family at its largest D (small calls leave the GPU
  * mostly idle, so one iteration of one wave is their latency). Mixed calls
- * follow the same rule when every code takes the same family.
+ * follow the same rule at 2048 x D shots when every code takes the same
+ * family.
  * bpsf_tile_options writes the D values the code fits, most first, to host
  * d_out (up to cap) and returns their number. bpsf_set_tile fixes D and W
  * for later calls on the handle (0 = default: as above, as many waves as

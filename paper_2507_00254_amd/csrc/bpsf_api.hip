@@ -136,10 +136,19 @@ bool tile_fits(const bpsf_code_s* c, int fam, int D)
 // decodes per wave D, when it has at most SMALL_CALL_SHOTS_PER_D * D shots:
 // such calls do not fill the GPU, so their time is the iterations of one
 // decode, and one iteration of a wave is about twice as fast with a third of
-// the items. Measured on [[144]] (D = 2 there) the small family is faster up
-// to about 16k shots, on [[288]] (D = 1) up to about 3k.
-constexpr int64_t SMALL_CALL_SHOTS_PER_D = 2048;
+// the items. Measured call times: on [[144]] (D = 2 there) the small family
+// is faster up to about 16k shots, on [[288]] (D = 1) about as fast at 4k.
+constexpr int64_t SMALL_CALL_SHOTS_PER_D = 4096;
+// The same for mixed calls, whose batches come from a serving loop under load
+// (at 3x10^6 shots/s offered, 3k-shot batches of five codes were slower on
+// the small family: p99 2.1 ms against 1.5 ms).
+constexpr int64_t SMALL_MIX_SHOTS_PER_D = 2048;
 constexpr int64_t SMALL_CALL_SHOTS = SMALL_CALL_SHOTS_PER_D * MAX_D;   // the most any code can use
+// Calls of at most this many shots per decode slot of a wave take tasks D at
+// a time instead of 2D, so all the trials of their few failed shots run at
+// once; measured on [[144]] (small family, D = 2): 256 shots 185 -> 164 us,
+// 1024 shots 201 -> 188 us, while 2048 and 4096 shots were slower with D.
+constexpr int64_t SMALL_CHUNK_SHOTS_PER_D = 512;
 
 // Edges a lane of family `fam` works on per iteration.
 int family_items(int fam)
@@ -148,12 +157,12 @@ int family_items(int fam)
   return f.IC * f.W + f.IV * f.DV;
 }
 
-// Tile of a single-code call of `shots` shots (a forced D takes the family
-// with the fewest items per lane that fits at D; a small call that family at
-// its most decodes per wave), or, for shots < 0 (mixed calls, traces), the
-// default tile: the first family the code fits, at the most decodes per wave
-// (the handle's tuned or forced D when set).
-int pick_tile(const bpsf_code_s* c, TileDesc* out, int64_t shots = -1)
+// Tile of a call of `shots` shots (a forced D takes the family with the
+// fewest items per lane that fits at D; a call of at most per_d x D shots that
+// family at its most decodes per wave D), or, for shots < 0 (the default of
+// mixed handles, traces) and larger calls, the first family the code fits, at
+// the most decodes per wave (the handle's tuned or forced D when set).
+int pick_tile(const bpsf_code_s* c, TileDesc* out, int64_t shots = -1, int64_t per_d = SMALL_CALL_SHOTS_PER_D)
 {
   if (shots >= 0) {
     int best = -1, best_D = 0;
@@ -171,7 +180,7 @@ int pick_tile(const bpsf_code_s* c, TileDesc* out, int64_t shots = -1)
       }
     }
     if (best < 0) return -1;
-    if (c->tuned_D > 0 || shots <= SMALL_CALL_SHOTS_PER_D * best_D) {
+    if (c->tuned_D > 0 || shots <= per_d * best_D) {
       *out = TileDesc{best, best_D};
       return 0;
     }
@@ -426,6 +435,7 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
   int rc = fill_code_args(c, p, t, &a);
   if (rc) return rc;
   a.shots = shots;
+  if (t.D > 0 && shots <= SMALL_CHUNK_SHOTS_PER_D * t.D) a.chunk = t.D;
   // scratch: one record and key per shot at most
   const int64_t cap = shots > 0 ? shots : 1;
   if (c->records.ensure(sizeof(int32_t) * (size_t)a.rec_stride * (size_t)cap) ||
@@ -1005,7 +1015,7 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
   bool small = only < 0 && shots <= SMALL_CALL_SHOTS;
   for (int i = 0, f0 = -1; i < m->n && small; ++i) {
     TileDesc t;
-    if (pick_tile(m->codes[i], &t, shots) || (f0 >= 0 && t.fam != f0)) {
+    if (pick_tile(m->codes[i], &t, shots, SMALL_MIX_SHOTS_PER_D) || (f0 >= 0 && t.fam != f0)) {
       small = false;
     } else {
       f0 = t.fam;
@@ -1019,11 +1029,12 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
     if (i == only) {
       if (pick_tile(c, &tiles[i], counts[i])) return fail(BPSF_ENOTSUP, "code %d has no kernel tile", i);
     } else if (small) {
-      if (pick_tile(c, &tiles[i], shots)) return fail(BPSF_ENOTSUP, "code %d has no kernel tile", i);
+      if (pick_tile(c, &tiles[i], shots, SMALL_MIX_SHOTS_PER_D)) return fail(BPSF_ENOTSUP, "code %d has no kernel tile", i);
     } else if (pick_tile(c, &tiles[i]) || tiles[i].fam != m->fam) {
       return fail(BPSF_ENOTSUP, "code %d changed kernel family", i);
     }
     if ((rc = fill_code_args(c, p, tiles[i], &ma.code[i]))) return rc;
+    if ((i == only ? counts[i] : shots) <= SMALL_CHUNK_SHOTS_PER_D * tiles[i].D) ma.code[i].chunk = tiles[i].D;
     // a mixed launch runs the uniform-LLR kernel only when every code qualifies
     lds = std::max(lds, tile_lds(c, tiles[i], fp64, uniform));
     stride = std::max(stride, ma.code[i].rec_stride);

@@ -54,19 +54,21 @@ def test_autotune_picks_a_listed_tile_and_keeps_results():
 
 
 def test_small_and_large_calls_agree():
-    """A call of more than 2048 x D shots (D: the small family's decodes per
+    """A call of more than 4096 x D shots (D: the small family's decodes per
     wave for the code) runs the large family at its most decodes per wave,
-    smaller calls the family with the fewest items per lane: the same shots
-    decoded both ways give identical results, equal to the oracle's."""
+    smaller calls the family with the fewest items per lane (and calls of at
+    most 512 x D shots take D tasks at a time): the same shots decoded both
+    ways give identical results, equal to the oracle's."""
     from paper_2507_00254_amd import bpsf as B
     for name, p in (("bb144", 0.05), ("bb288", 0.04), ("bb72", 0.06)):
-        code, _, syn = U.inputs(name, p, 9000, tag=22)
+        code, _, syn = U.inputs(name, p, 18000, tag=22)
         prm = U.oracle_params(k=6)
         h = B.bpsf_load_code(code.hx)
         try:
-            print(f"{name}: one call of 9000, then 6 x 1500", flush=True)
+            print(f"{name}: one call of 18000, then 1500-shot and 300-shot calls", flush=True)
             big = U.gpu_decode(code.hx, syn, p, prm, handle=h)
-            parts = [U.gpu_decode(code.hx, syn[i:i + 1500], p, prm, handle=h) for i in range(0, 9000, 1500)]
+            cuts = list(range(0, 9000, 1500)) + list(range(9000, 18000, 300)) + [18000]
+            parts = [U.gpu_decode(code.hx, syn[a:b], p, prm, handle=h) for a, b in zip(cuts[:-1], cuts[1:])]
             for f in ("correction", "converged", "iterations"):
                 assert np.array_equal(big[f], np.concatenate([q[f] for q in parts])), (name, f)
             o = U.oracle_decode(code.hx, syn[:1500], p, prm, precision="f32")
