@@ -300,7 +300,9 @@ def run_dem(args):
     n_s = 5 sampled trials per weight 1..6 (30 trials of 100 iterations),
     first success kept with pruning; float messages (sparse kernel family).
     A fourth point runs p = 0.003 with |Phi| = 50 and n_s = 10 per weight
-    1..10 (100 trials). Each point also times single-syndrome calls."""
+    1..10 (100 trials), a fifth [[288,12,18]] over 6 rounds at p = 0.003
+    (1008 x 8928, about the size of the [[144]] model). Each point also
+    times single-syndrome calls."""
     import torch
 
     from paper_2507_00254_amd import bpsf as B
@@ -321,9 +323,13 @@ def run_dem(args):
     prm50 = B.make_params(max_iter=100, cand_max_iter=100, k=50, cand_mode=B.TRIALS_TABLE, select_mode=1,
                           alpha=0.0, flags=B.FLAG_PRUNE, precision=B.PREC_FP32)
     rows = []
-    for p, phi in ((0.001, 16), (0.002, 16), (0.003, 16), (0.003, 50)):
-        dem = circuit.build_dem(c.hx, c.hz, 12, p)
-        err, syn, obs = circuit.sample(dem, n, shots.stream_key(shots.MASTER_SEED, 1501, int(round(p * 1e5))))
+    c288 = codes.bb288()
+    points = [(c, 12, 0.001, 16), (c, 12, 0.002, 16), (c, 12, 0.003, 16), (c, 12, 0.003, 50),
+              (c288, 6, 0.003, 16)]
+    for code, rounds, p, phi in points:
+        dem = circuit.build_dem(code.hx, code.hz, rounds, p)
+        salt = int(round(p * 1e5)) if code is c else 1_000_000 + int(round(p * 1e5))
+        err, syn, obs = circuit.sample(dem, n, shots.stream_key(shots.MASTER_SEED, 1501, salt))
         handle = B.bpsf_load_code(dem.h)
         edges = B.bpsf_code_info(handle)["edges"]
         B.bpsf_set_trial_table(handle, d_masks if phi == 16 else d_masks50)
@@ -351,12 +357,13 @@ def run_dem(args):
             ev1.synchronize()
             lat.append(ev0.elapsed_time(ev1) * 1e3)
         lat = np.array(lat) if lat else np.array([np.nan])
-        rows.append({"p": p, "phi": phi, "trials": int(len(masks) if phi == 16 else len(masks50)),
+        rows.append({"code": code.name, "rounds": rounds, "p": p, "phi": phi,
+                     "trials": int(len(masks) if phi == 16 else len(masks50)),
                      "shots": n, "mechanisms": int(dem.h.shape[1]), "edges": edges,
                      "ms_per_step": ms, "value": n / (ms * 1e-3), "phases_ms": avg,
                      "mean_latency_iterations": float(it.float().mean().item()),
                      "work": {**iters, "failed_shots": st["failed_shots"], "errors": st["errors"]},
-                     "ler": ler, "ler_per_round": 1.0 - (1.0 - ler) ** (1.0 / 12),
+                     "ler": ler, "ler_per_round": 1.0 - (1.0 - ler) ** (1.0 / rounds),
                      "syndrome_latency_us": {"calls": int(len(lat)), "mean": float(lat.mean()),
                                              "p50": float(np.percentile(lat, 50)),
                                              "p99": float(np.percentile(lat, 99)), "max": float(lat.max())},
@@ -366,7 +373,8 @@ def run_dem(args):
                                               f"iterations"}})
         print(json.dumps(rows[-1]), flush=True)
         B.bpsf_free_code(handle)
-    print(json.dumps({"metric": "decoded shots/s, circuit-level [[144,12,12]] detector error model, d = 12",
+    print(json.dumps({"metric": "decoded shots/s, circuit-level detector error models of [[144,12,12]] (d = 12 "
+                                "rounds) and [[288,12,18]] (6 rounds)",
                       "unit": "shots/s", "n_gpus": 1, "dtype": "f32",
                       "data": "synthetic (mechanisms sampled from a self-built detector error model)",
                       "config": {"workload": "dem144_d12_2e4", "max_iter": 100, "k": [16, 50],

@@ -28,7 +28,10 @@ def _decode_table(h, syn, pri, prm, masks):
     return dt(h, syn, pri, prm, masks)
 
 
-@pytest.mark.parametrize("name,rounds,p,n", [("bb144", 12, 0.003, 300), ("bb72", 6, 0.004, 600)])
+# [[288,12,18]] over 6 rounds (1008 x 8928, 34,452 edges) is about as large as
+# [[144,12,12]] over 12 and fits the same sparse family
+@pytest.mark.parametrize("name,rounds,p,n", [("bb144", 12, 0.003, 300), ("bb72", 6, 0.004, 600),
+                                             ("bb288", 6, 0.003, 200)])
 @pytest.mark.parametrize("select", [1, 0])
 def test_dem_parity_sampled_trials(name, rounds, p, n, select):
     dem = _dem(name, rounds, p)
