@@ -17,6 +17,7 @@ def test_every_tile_gives_the_same_results(name, p):
     try:
         opts = B.bpsf_tile_options(h)
         assert opts and opts == sorted(opts, reverse=True) and all(64 % d == 0 for d in opts)
+        assert len(set(opts)) == len(opts)      # each D once, whichever families fit it
         ref = U.gpu_decode(code.hx, syn, p, prm, handle=h)
         o = U.oracle_decode(code.hx, syn, p, prm, precision="f32")
         assert len(U.mismatches(ref, o)) == 0
