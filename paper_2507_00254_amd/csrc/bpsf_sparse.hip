@@ -324,8 +324,9 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
             for (int q = 0; q < CH; ++q) {
               m2 = R::med3(m1, m2, R::absr(x[q]));
               m1 = R::minr(m1, R::absr(x[q]));
-              P ^= R::sw(x[q]);
             }
+#pragma unroll
+            for (int q = 0; q < CH; q += 2) P = xor3(P, R::sw(x[q]), R::sw(x[q + 1]));   // two signs per op
           } else if ((uint32_t)jc < rb) {
             // the last, partial chunk: positions up to the wave's bound only
 #pragma unroll

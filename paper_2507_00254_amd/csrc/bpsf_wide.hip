@@ -209,14 +209,17 @@ __device__ __forceinline__ void decode_wide(const Args& a)
           }
           Real m1 = R::minr(R::absr(xc[0]), R::absr(xc[1]));
           Real m2 = R::maxr(R::absr(xc[0]), R::absr(xc[1]));
-          uint32_t P = R::sw(xc[0]) ^ R::sw(xc[1]);
 #pragma unroll
           for (int j = 2; j < W; ++j) {
             m2 = R::med3(m1, m2, R::absr(xc[j]));
             m1 = R::minr(m1, R::absr(xc[j]));
-            P ^= R::sw(xc[j]);
           }
-          P ^= synbits << (31 - k);
+          // sign parity, (-1)^{s_c} included, in bit 31; two signs per op
+          // (padding holds +inf, which adds no sign)
+          uint32_t P = synbits << (31 - k);
+#pragma unroll
+          for (int j = 0; j + 1 < W; j += 2) P = xor3(P, R::sw(xc[j]), R::sw(xc[j + 1]));
+          if constexpr (W % 2 != 0) P ^= R::sw(xc[W - 1]);
           Real s1 = R::flip(alpha * m1, P), s2 = R::flip(alpha * m2, P);
           R::opaque(s1);
           R::opaque(s2);
