@@ -86,6 +86,25 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t x)
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
 }
 
+// The message cell named by half h (0: low, 1: high) of a packed word of
+// 16-bit cell indices. Messages start at LDS byte 0 (the kernel has no static
+// LDS, checked on the host before every launch), so the byte address is the
+// index times four: one shift of a 16-bit operand, with no base to add.
+__device__ __forceinline__ __attribute__((address_space(3))) float& cell_ref(unsigned char* smem, uint32_t w, int h)
+{
+  (void)smem;
+  uint32_t b;
+  if (h) {
+    b = (w >> 16) << 2;
+  } else {
+    // the low half shifted in one instruction (the compiler rewrites the
+    // mask-then-shift into two)
+    asm("v_lshlrev_b32_sdwa %0, 2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_0"
+        : "=v"(b) : "v"(w));
+  }
+  return *(__attribute__((address_space(3))) float*)(size_t)b;
+}
+
 template <int NW, int CPT, int WMAX, int BPT, int DVMAX, int MODE>
 __device__ __forceinline__ void decode_sparse(const Args& a)
 {
@@ -318,7 +337,7 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
 #pragma unroll
             for (int q = 0; q < CH; ++q) {
               const int j = jc + q;
-              x[q] = msg[(j & 1) ? (roff[i][j >> 1] >> 16) : (roff[i][j >> 1] & 0xffffu)];
+              x[q] = cell_ref(smem, roff[i][j >> 1], j & 1);
             }
 #pragma unroll
             for (int q = 0; q < CH; ++q) {
@@ -333,7 +352,7 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
             for (int q = 0; q < CH; ++q) {
               const int j = jc + q;
               if ((uint32_t)j < rb) {
-                const float x = msg[(j & 1) ? (roff[i][j >> 1] >> 16) : (roff[i][j >> 1] & 0xffffu)];
+                const float x = cell_ref(smem, roff[i][j >> 1], j & 1);
                 m2 = R::med3(m1, m2, R::absr(x));
                 m1 = R::minr(m1, R::absr(x));
                 P ^= R::sw(x);
@@ -351,23 +370,24 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
         for (int jc = 0; jc < WMAX; jc += CH) {
           if ((uint32_t)jc + CH <= rb) {
             float x[CH];
-            uint32_t cell[CH];
 #pragma unroll
             for (int q = 0; q < CH; ++q) {
               const int j = jc + q;
-              cell[q] = (j & 1) ? (roff[i][j >> 1] >> 16) : (roff[i][j >> 1] & 0xffffu);
-              x[q] = msg[cell[q]];
+              x[q] = cell_ref(smem, roff[i][j >> 1], j & 1);
             }
 #pragma unroll
-            for (int q = 0; q < CH; ++q) msg[cell[q]] = R::flip(R::absr(x[q]) == m1 ? s2 : s1, R::sw(x[q]));
+            for (int q = 0; q < CH; ++q) {
+              const int j = jc + q;
+              cell_ref(smem, roff[i][j >> 1], j & 1) = R::flip(R::absr(x[q]) == m1 ? s2 : s1, R::sw(x[q]));
+            }
           } else if ((uint32_t)jc < rb) {
 #pragma unroll
             for (int q = 0; q < CH; ++q) {
               const int j = jc + q;
               if ((uint32_t)j < rb) {
-                const uint32_t cell = (j & 1) ? (roff[i][j >> 1] >> 16) : (roff[i][j >> 1] & 0xffffu);
-                const float x = msg[cell];
-                msg[cell] = R::flip(R::absr(x) == m1 ? s2 : s1, R::sw(x));
+                __attribute__((address_space(3))) float& cx = cell_ref(smem, roff[i][j >> 1], j & 1);
+                const float x = cx;
+                cx = R::flip(R::absr(x) == m1 ? s2 : s1, R::sw(x));
               }
             }
           }
@@ -557,6 +577,15 @@ __global__ __launch_bounds__(64 * NW) void bpsf_sparse_kernel(Args a)
 template <int NW, int CPT, int WMAX, int BPT, int DVMAX, int MODE>
 int run_sparse_mode(int what, const Args& a, size_t lds, int grid, hipStream_t st, int* out)
 {
+  // the row gathers address messages from LDS byte 0 (cell_ref): the kernel
+  // must have no static LDS ahead of its dynamic array
+  static const bool lds_at_zero = [] {
+    hipFuncAttributes fa;
+    return hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(bpsf_sparse_kernel<NW, CPT, WMAX, BPT, DVMAX, MODE>)) ==
+               hipSuccess &&
+           fa.sharedSizeBytes == 0;
+  }();
+  if (!lds_at_zero) return -1;
   // a workgroup may use more than 64 KiB of LDS once the kernel allows it
   if (hipFuncSetAttribute(reinterpret_cast<const void*>(bpsf_sparse_kernel<NW, CPT, WMAX, BPT, DVMAX, MODE>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
