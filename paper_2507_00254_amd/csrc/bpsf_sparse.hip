@@ -28,6 +28,8 @@
 //   * a failed first BP leaves a record holding its Phi; a trial rebuilds
 //     s' = s + t H^T from the shot's syndrome and the columns of Phi.
 #include <hip/hip_runtime.h>
+
+#include <atomic>
 #include <math.h>
 #include <stdint.h>
 
@@ -587,9 +589,22 @@ int run_sparse_mode(int what, const Args& a, size_t lds, int grid, hipStream_t s
   }();
   if (!lds_at_zero) return -1;
   // a workgroup may use more than 64 KiB of LDS once the kernel allows it
-  if (hipFuncSetAttribute(reinterpret_cast<const void*>(bpsf_sparse_kernel<NW, CPT, WMAX, BPT, DVMAX, MODE>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-    return -1;
+  // (raised once per device and size, not before every launch)
+  constexpr int MAX_DEVICES = 64;
+  static std::atomic<size_t> allowed[MAX_DEVICES];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  std::atomic<size_t>* al = dev >= 0 && dev < MAX_DEVICES ? &allowed[dev] : nullptr;
+  if (!al || lds > al->load(std::memory_order_relaxed)) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(bpsf_sparse_kernel<NW, CPT, WMAX, BPT, DVMAX, MODE>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      return -1;
+    if (al) {
+      size_t cur = al->load(std::memory_order_relaxed);
+      while (lds > cur && !al->compare_exchange_weak(cur, lds, std::memory_order_relaxed)) {
+      }
+    }
+  }
   if (what == 1)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bpsf_sparse_kernel<NW, CPT, WMAX, BPT, DVMAX, MODE>,
                                                         64 * NW, lds) == hipSuccess ? 0 : -1;
