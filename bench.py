@@ -599,7 +599,7 @@ def main():
     lat = np.array(lat) if lat else np.array([np.nan])
 
     out = {
-        "metric": "decoded shots/s at [[144,12,12]] p=0.03 (BP-SF); p99 decode latency (us)",
+        "metric": f"decoded shots/s at [[144,12,12]] p={p:g} (BP-SF); p99 decode latency (us)",
         "value": n / (ms_per_step * 1e-3),
         "unit": "shots/s",
         "n_gpus": 1,
