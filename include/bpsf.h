@@ -149,9 +149,11 @@ int bpsf_decode(bpsf_code code, const uint8_t* syndromes, const double* priors, 
 
 /*
  * Grow the handle's scratch now for calls of up to `shots` shots with these
- * parameters (their k and the code's launch shape set the record size), so
- * that such calls allocate nothing: for callers that cannot allocate later,
- * e.g. under HIP graph capture or in a serving loop. Synchronous.
+ * parameters (their k and the launch shape set the record size; every shape
+ * a call of up to `shots` shots can take is covered, the small family's
+ * longer records included), so that such calls allocate nothing: for
+ * callers that cannot allocate later, e.g. under HIP graph capture or in a
+ * serving loop. Synchronous.
  */
 int bpsf_reserve(bpsf_code code, int64_t shots, const bpsf_params* params);
 
