@@ -711,7 +711,8 @@ __device__ __forceinline__ void decode_code(const Args& a, bool own_first)
 
 // Waves per SIMD the register allocator keeps room for: three for the float
 // kernels of the row-weight-6 family with uniform priors, whose LDS allows ten
-// waves per CU (a few registers over the limit would halve that to eight)
+// waves per CU (a few registers over the limit would cut that to eight); the
+// mixed kernel of that family too (nine to ten waves per CU by its LDS)
 template <typename Real, int W, bool UL, bool TRACE, bool LAY>
 constexpr int min_waves_per_simd() { return (sizeof(Real) == 4 && W == 6 && UL && !TRACE && !LAY) ? 3 : 1; }
 
@@ -748,7 +749,8 @@ __device__ __forceinline__ long long phase_tasks(const Args& a)
 // takes the codes after it in turn, so waves whose code runs out help the
 // others.
 template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE>
-__global__ __launch_bounds__(64) void bpsf_mixed_kernel(const MixArgs m)
+__global__ __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(min_waves_per_simd<Real, W, UL, false, false>()))) void bpsf_mixed_kernel(const MixArgs m)
 {
   // every code's task and taken counts in one round trip: lane c loads code c's
   const int lane = threadIdx.x;
