@@ -416,8 +416,13 @@ __device__ __forceinline__ void decode_wide(const Args& a)
   }
 }
 
+// The float trial and re-run kernels are held to three waves per SIMD (168
+// VGPRs, a few bytes of scratch outside the iteration loop): four workgroups
+// of three waves per CU instead of two, as the LDS allows. The first-BP kernel
+// would spill inside its loop and stays at two.
 template <typename Real, int NW, int IC, int IV, int W, int DV, int MODE>
-__global__ __launch_bounds__(64 * NW) void bpsf_wide_kernel(Args a)
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 && MODE != MODE_MAIN ? 3 : 1)))
+void bpsf_wide_kernel(Args a)
 {
   decode_wide<Real, NW, IC, IV, W, DV, MODE>(a);
 }
