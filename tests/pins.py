@@ -250,6 +250,42 @@ def pin_empty_trial(O):
     assert fails >= 1
 
 
+def pin_trials_independent(O):
+    """Algorithm 1 decodes every trial syndrome s' = s + t H^T with its own
+    BP(s'): for every trial vector of a failed shot, the trial's recorded
+    outcome (converged, iterations, weight of e' + t) equals a separate plain
+    BP run on s' from fresh messages, undone by t. A trial that inherited any
+    state of the first BP or of the previous trial (messages, the damping
+    schedule) would differ from the separate run."""
+    cases = ((codes.bb72(), 0.1, Params(max_iter=30, cand_max_iter=12, k=4)),
+             (codes.bb144(), 0.07, Params(max_iter=25, cand_max_iter=15, k=5)),
+             (codes.bb144(), 0.07, Params(max_iter=25, cand_max_iter=15, k=4, alpha=0.0)))
+    for code, p, prm in cases:
+        h = code.hx
+        _, syn = _shots(code, p, 200, 6)
+        masks = O.trial_masks(prm)
+        seen = 0
+        for i in range(len(syn)):
+            d = O.bpsf_detail(h, syn[i], p, prm)
+            if d["main_converged"]:
+                continue
+            phi = [int(v) for v in d["phi"]]
+            for ti, mask in enumerate(masks):
+                t = np.zeros(code.n, np.uint8)
+                for j in range(prm.k):
+                    if (int(mask) >> j) & 1:
+                        t[phi[j]] = 1
+                b = O.bp(h, syn[i] ^ syndrome(h, t), p, prm, max_iter=prm.cand_max_iter)
+                assert d["trial_converged"][ti] == b["converged"], (code.name, i, ti)
+                assert d["trial_iterations"][ti] == b["iterations"], (code.name, i, ti)
+                want_w = int((b["hard"] ^ t).sum()) if b["converged"] else -1
+                assert d["trial_weight"][ti] == want_w, (code.name, i, ti)
+            seen += 1
+            if seen >= 3:
+                break
+        assert seen >= 1, code.name
+
+
 def pin_trial_vectors(O):
     """Trial enumeration: all 2^k subsets (bit j <-> Phi[j]), or the
     combinations of weight 1..w_max in order; the iteration budgets printed in
@@ -398,5 +434,6 @@ def pin_wide_trial_masks(O):
 
 PINS = [pin_tree_min_sum, pin_tree_sum_product, pin_first_iteration_closed_form, pin_zero_syndrome,
         pin_half_prior, pin_ml_identity, pin_converged_invariant, pin_flip_counts, pin_empty_trial,
+        pin_trials_independent,
         pin_trial_vectors, pin_trial_results, pin_scale_invariance, pin_layered_tree, pin_layered_chain,
         pin_layered_ml_identity, pin_wide_trial_masks]

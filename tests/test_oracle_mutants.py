@@ -38,6 +38,8 @@ MUTANTS = [
     ("top_k_ascending", "w->flips[v] > w->flips[bi]", "w->flips[v] < w->flips[bi]"),
     ("top_k_ties_to_high_index", "w->flips[v] > w->flips[bi]", "w->flips[v] >= w->flips[bi]"),
     ("trial_syndrome_not_flipped", "par ^= t[g->col_idx[e]];", "(void)t;"),
+    ("trial_messages_not_reset", "for (int e = 0; e < E; e++) w->c2v[e] = (real)0;",
+     "if (track) for (int e = 0; e < E; e++) w->c2v[e] = (real)0;"),
     ("trial_output_not_undone", "for (int v = 0; v < N; v++) w->hard[v] ^= t[v];", "(void)t;"),
     ("selection_keeps_heaviest", "wt < best_w", "wt > best_w"),
     ("layered_posterior_not_written", "w->lout[g->col_idx[e]] = w->v2c[e] + w->c2v[e];", "(void)0;"),
