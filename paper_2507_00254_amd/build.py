@@ -16,11 +16,13 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbpsf.so")
+PROBE_LIB = os.path.join(HERE, "liblds_probe.so")
 ARCH = os.environ.get("BPSF_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-variable",
           "-Wno-unused-but-set-variable"]
+# units of libbpsf.so (lds_probe.hip builds liblds_probe.so on its own)
 UNITS = [("bpsf_kernels.hip", ["-fno-honor-nans"]), ("bpsf_wide.hip", ["-fno-honor-nans"]),
          ("bpsf_sparse.hip", ["-fno-honor-nans"]), ("bpsf_api.hip", []), ("bpsf_server.hip", [])]
 
@@ -40,6 +42,11 @@ def build(verbose: bool = False) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     objs, procs = [], []
+    # the LDS bandwidth probe: a library of its own (include/lds_probe.h)
+    probe_cmd = ["hipcc", *COMMON, "-shared", os.path.join(CSRC, "lds_probe.hip"), "-o", PROBE_LIB + ".tmp"]
+    if verbose:
+        print(" ".join(probe_cmd), flush=True)
+    procs.append((subprocess.Popen(probe_cmd), probe_cmd))
     # the units compile in parallel (at most four at a time)
     for src, extra in UNITS:
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
@@ -58,6 +65,7 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    os.replace(PROBE_LIB + ".tmp", PROBE_LIB)
     return LIB
 
 
