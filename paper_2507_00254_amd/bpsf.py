@@ -45,6 +45,15 @@ class BpsfError(RuntimeError):
         self.code = code
 
 
+class BpsfArgumentError(BpsfError, ValueError):
+    """An argument the binding rejects before calling the library (a tensor of
+    the wrong shape, element type or device, or a priors array of the wrong
+    length): the library would read or write out of bounds with it."""
+
+    def __init__(self, msg):
+        super().__init__(BPSF_EINVAL, msg)
+
+
 def _load():
     # torch brings its own HIP runtime; it has to be in the process before
     # this library resolves libamdhip64, or torch later finds no GPU
@@ -150,16 +159,68 @@ def _stream_ptr(stream):
     return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
 
+def _tensor(t, name, dtype, ndim):
+    """A contiguous device tensor of the given element type and rank."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise BpsfArgumentError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise BpsfArgumentError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() != ndim:
+        raise BpsfArgumentError(f"{name} must have {ndim} dimension(s), got shape {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise BpsfArgumentError(f"{name} must be contiguous")
+    return t
+
+
+def _outputs(corrections, converged, iterations, shots, n_min, exact_n=None):
+    """Output tensors able to hold `shots` results: corrections uint8 [>= shots,
+    N] (N == exact_n, or >= n_min), converged uint8 [>= shots], iterations
+    int32 [>= shots]."""
+    import torch
+    _tensor(corrections, "corrections", torch.uint8, 2)
+    _tensor(converged, "converged", torch.uint8, 1)
+    _tensor(iterations, "iterations", torch.int32, 1)
+    if corrections.shape[0] < shots:
+        raise BpsfArgumentError(f"corrections has {corrections.shape[0]} rows for {shots} shots")
+    if exact_n is not None and corrections.shape[1] != exact_n:
+        raise BpsfArgumentError(f"corrections rows must hold N = {exact_n} bits, got {corrections.shape[1]}")
+    if corrections.shape[1] < n_min:
+        raise BpsfArgumentError(f"corrections rows must hold at least {n_min} bits, got {corrections.shape[1]}")
+    if converged.shape[0] < shots or iterations.shape[0] < shots:
+        raise BpsfArgumentError(f"converged and iterations need at least {shots} entries")
+
+
+def _priors_of(priors, n, what="priors"):
+    pri = np.ascontiguousarray(priors, dtype=np.float64)
+    if pri.ndim != 1 or pri.shape[0] != n:
+        raise BpsfArgumentError(f"{what} must be a 1-D array of N = {n} probabilities, got shape {pri.shape}")
+    return pri
+
+
+def _on_device(*ts):
+    for t in ts:
+        if not t.is_cuda:
+            raise BpsfArgumentError("device tensors must be CUDA (HIP) tensors")
+
+
 def bpsf_decode(handle, syndromes, priors, params: bpsf_params, corrections, converged, iterations,
                 stream=None) -> None:
     """Enqueue a decode. ``syndromes`` uint8 [shots, M], ``corrections`` uint8
     [shots, N], ``converged`` uint8 [shots], ``iterations`` int32 [shots] are
-    torch tensors on the GPU; ``priors`` is a host array of N probabilities."""
-    pri = np.ascontiguousarray(priors, dtype=np.float64)
+    torch tensors on the GPU; ``priors`` is a host array of N probabilities.
+    Shapes and element types are checked here (the library takes rows of M
+    and N bytes)."""
+    import torch
+    info = bpsf_code_info(handle)
+    m, n = info["M"], info["N"]
+    _tensor(syndromes, "syndromes", torch.uint8, 2)
+    if syndromes.shape[1] != m:
+        raise BpsfArgumentError(f"syndromes rows must hold M = {m} checks, got {syndromes.shape[1]}")
     shots = int(syndromes.shape[0])
-    for t in (syndromes, corrections, converged, iterations):
-        if not t.is_cuda or not t.is_contiguous():
-            raise ValueError("device tensors must be contiguous CUDA (HIP) tensors")
+    _outputs(corrections, converged, iterations, shots, n, exact_n=n)
+    pri = _priors_of(priors, n)
+    _on_device(syndromes, corrections, converged, iterations)
     _check(LIB.bpsf_decode(C.c_void_p(handle), C.c_void_p(syndromes.data_ptr()),
                            pri.ctypes.data_as(C.POINTER(C.c_double)), shots, C.byref(params),
                            C.c_void_p(corrections.data_ptr()), C.c_void_p(converged.data_ptr()),
@@ -225,7 +286,13 @@ def bpsf_set_tile(handle, decodes_per_wave: int = 0, waves_per_cu: int = 0) -> N
 
 def bpsf_autotune(handle, syndromes, priors, params: bpsf_params, reps: int = 3, stream=None) -> dict:
     """Time every launch shape on a device sample of syndromes; keep the fastest."""
-    pri = np.ascontiguousarray(priors, dtype=np.float64)
+    import torch
+    info = bpsf_code_info(handle)
+    _tensor(syndromes, "syndromes", torch.uint8, 2)
+    if syndromes.shape[1] != info["M"]:
+        raise BpsfArgumentError(f"syndromes rows must hold M = {info['M']} checks, got {syndromes.shape[1]}")
+    pri = _priors_of(priors, info["N"])
+    _on_device(syndromes)
     out = bpsf_tuning()
     _check(LIB.bpsf_autotune(C.c_void_p(handle), C.c_void_p(syndromes.data_ptr()),
                              pri.ctypes.data_as(C.POINTER(C.c_double)), int(syndromes.shape[0]), C.byref(params),
@@ -238,11 +305,35 @@ def bpsf_mix_create(handles) -> int:
     arr = (C.c_void_p * len(handles))(*handles)
     out = C.c_void_p()
     _check(LIB.bpsf_mix_create(arr, len(handles), C.byref(out)))
+    _MIX_SHAPES[out.value] = [(i["M"], i["N"]) for i in (bpsf_code_info(h) for h in handles)]
     return out.value
 
 
+# (M, N) of every code of a mix handle, for argument checks
+_MIX_SHAPES: dict = {}
+
+
 def bpsf_mix_free(mix) -> None:
+    _MIX_SHAPES.pop(mix, None)
     LIB.bpsf_mix_free(mix)
+
+
+def _mix_args(mix, syndromes, priors, corrections, converged, iterations, shots):
+    import torch
+    shapes = _MIX_SHAPES.get(mix)
+    if shapes is None:
+        raise BpsfArgumentError("unknown mix handle (create it with bpsf_mix_create)")
+    _tensor(syndromes, "syndromes", torch.uint8, 2)
+    mmax = max(m for m, _ in shapes)
+    nmax = max(n for _, n in shapes)
+    if syndromes.shape[0] < shots:
+        raise BpsfArgumentError(f"syndromes has {syndromes.shape[0]} rows for {shots} shots")
+    if syndromes.shape[1] < mmax:
+        raise BpsfArgumentError(f"syndromes rows must hold the largest M = {mmax}, got {syndromes.shape[1]}")
+    _outputs(corrections, converged, iterations, shots, nmax)
+    if len(priors) != len(shapes):
+        raise BpsfArgumentError(f"need one priors array per code ({len(shapes)}), got {len(priors)}")
+    return [_priors_of(x, n, f"priors[{c}]") for c, (x, (_, n)) in enumerate(zip(priors, shapes))]
 
 
 def bpsf_mix_decode(mix, shot_code, syndromes, priors, params: bpsf_params, corrections, converged, iterations,
@@ -252,11 +343,11 @@ def bpsf_mix_decode(mix, shot_code, syndromes, priors, params: bpsf_params, corr
     [shots, corr_stride], ``converged`` uint8 [shots], ``iterations`` int32
     [shots] are device tensors; ``priors`` is a list of host arrays, one per
     code of the mix."""
+    import torch
+    _tensor(shot_code, "shot_code", torch.int32, 1)
     shots = int(shot_code.shape[0])
-    for t in (shot_code, syndromes, corrections, converged, iterations):
-        if not t.is_cuda or not t.is_contiguous():
-            raise ValueError("device tensors must be contiguous CUDA (HIP) tensors")
-    pri = [np.ascontiguousarray(x, dtype=np.float64) for x in priors]
+    pri = _mix_args(mix, syndromes, priors, corrections, converged, iterations, shots)
+    _on_device(shot_code, syndromes, corrections, converged, iterations)
     parr = (C.POINTER(C.c_double) * len(pri))(*[x.ctypes.data_as(C.POINTER(C.c_double)) for x in pri])
     _check(LIB.bpsf_mix_decode(C.c_void_p(mix), C.c_void_p(shot_code.data_ptr()), C.c_void_p(syndromes.data_ptr()),
                                int(syndromes.shape[1]), parr, shots, C.byref(params),
@@ -270,10 +361,13 @@ def bpsf_mix_decode_grouped(mix, counts, syndromes, priors, params: bpsf_params,
     """As bpsf_mix_decode with code c's shots the counts[c] rows after those
     of the codes before it."""
     cnt = np.ascontiguousarray(counts, dtype=np.int64)
-    for t in (syndromes, corrections, converged, iterations):
-        if not t.is_cuda or not t.is_contiguous():
-            raise ValueError("device tensors must be contiguous CUDA (HIP) tensors")
-    pri = [np.ascontiguousarray(x, dtype=np.float64) for x in priors]
+    shapes = _MIX_SHAPES.get(mix)
+    if shapes is not None and (cnt.ndim != 1 or cnt.shape[0] != len(shapes)):
+        raise BpsfArgumentError(f"counts must hold one entry per code ({len(shapes)})")
+    if (cnt < 0).any():
+        raise BpsfArgumentError("counts must be >= 0")
+    pri = _mix_args(mix, syndromes, priors, corrections, converged, iterations, int(cnt.sum()))
+    _on_device(syndromes, corrections, converged, iterations)
     parr = (C.POINTER(C.c_double) * len(pri))(*[x.ctypes.data_as(C.POINTER(C.c_double)) for x in pri])
     _check(LIB.bpsf_mix_decode_grouped(C.c_void_p(mix), cnt.ctypes.data_as(C.POINTER(C.c_int64)),
                                        C.c_void_p(syndromes.data_ptr()), int(syndromes.shape[1]), parr,
@@ -306,6 +400,11 @@ class Server:
                                                           for x in self._pri])
         arr = (C.c_void_p * len(handles))(*handles)
         out = C.c_void_p()
+        self._shapes = [(i["M"], i["N"]) for i in (bpsf_code_info(h) for h in handles)]
+        if len(self._pri) != len(handles):
+            raise BpsfArgumentError(f"need one priors array per code ({len(handles)}), got {len(self._pri)}")
+        for c, (x, (_, n)) in enumerate(zip(self._pri, self._shapes)):
+            _priors_of(x, n, f"priors[{c}]")
         _check(LIB.bpsf_server_create(arr, len(handles), parr, C.byref(params), int(lanes), int(max_batch_shots),
                                       int(bool(batching)), C.byref(out)))
         self.h = out.value
@@ -314,7 +413,7 @@ class Server:
     def submit(self, code: int, syndromes: np.ndarray):
         """Enqueue host syndromes uint8 [n, M]; returns (id, corrections,
         converged, iterations) whose arrays fill in once the request is done."""
-        syn = np.ascontiguousarray(syndromes, dtype=np.uint8)
+        syn = self._syndromes(code, syndromes)
         n = syn.shape[0]
         nbits = self._n_of(code)
         corr = np.empty((n, nbits), np.uint8)
@@ -346,7 +445,9 @@ class Server:
         n = len(codes)
         arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
         cd = np.ascontiguousarray(codes, dtype=np.int32)
-        syns = [np.ascontiguousarray(x, dtype=np.uint8) for x in syndromes]
+        if len(syndromes) != n or arr.shape != (n,):
+            raise BpsfArgumentError("arrival_s, codes and syndromes must have one entry per request")
+        syns = [self._syndromes(int(c), x) for c, x in zip(cd, syndromes)]
         sh = np.array([x.shape[0] for x in syns], np.int32)
         outs = [(np.empty((x.shape[0], self._n_of(int(c))), np.uint8), np.empty(x.shape[0], np.uint8),
                  np.empty(x.shape[0], np.int32)) for x, c in zip(syns, cd)]
@@ -377,7 +478,14 @@ class Server:
 
     def _n_of(self, code: int) -> int:
         # an out-of-range code is left for the library to reject
-        return len(self._pri[code]) if 0 <= code < len(self._pri) else 1
+        return self._shapes[code][1] if 0 <= code < len(self._shapes) else 1
+
+    def _syndromes(self, code: int, syndromes) -> np.ndarray:
+        """Host syndromes uint8 [n, M of the code] (the library copies n x M bytes)."""
+        syn = np.ascontiguousarray(syndromes, dtype=np.uint8)
+        if 0 <= code < len(self._shapes) and (syn.ndim != 2 or syn.shape[1] != self._shapes[code][0]):
+            raise BpsfArgumentError(f"syndromes of code {code} must be [n, {self._shapes[code][0]}], got {syn.shape}")
+        return syn
 
 
 def bpsf_code_info(handle) -> dict:
