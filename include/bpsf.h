@@ -132,7 +132,10 @@ void bpsf_free_code(bpsf_code code);
  *   priors      host, double [N], error probability p_v of every bit, each in
  *               (0, 1); channel LLR l_v = log((1 - p_v) / p_v) (Section II-B
  *               step 1) is computed on the host in double and cached on the
- *               device for the next call with the same priors
+ *               device for the next call with the same priors; a call whose
+ *               priors differ from the handle's last ones (or whose trial set
+ *               differs) first waits for the work already enqueued on
+ *               `stream`, which may still read the old tables
  *   params      host; see bpsf_params
  *   corrections device, uint8 [shots][N]: the estimate e (0/1); when no trial
  *               succeeds it is the first BP's last hard decision

@@ -256,9 +256,18 @@ int check_params(const bpsf_params* p)
   return 0;
 }
 
+// The handle's device tables (LLRs, trial masks) are rewritten only after the
+// work already enqueued on the call's stream has finished: a decode still
+// queued there reads them. (The rewrite itself is a synchronous copy.)
+int drain_stream(void* stream)
+{
+  HIP_OK(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  return 0;
+}
+
 // Channel LLRs l_v = log((1 - p_v) / p_v) (Section II-B step 1), in double on
 // the host, then stored on the device in float and double.
-int update_llr(bpsf_code_s* c, const double* priors)
+int update_llr(bpsf_code_s* c, const double* priors, void* stream)
 {
   if (!priors) return fail(BPSF_EINVAL, "priors is NULL");
   if (!c->priors.empty() && memcmp(c->priors.data(), priors, sizeof(double) * (size_t)c->N) == 0) return 0;
@@ -269,6 +278,10 @@ int update_llr(bpsf_code_s* c, const double* priors)
     if (!(p > 0.0 && p < 1.0)) return fail(BPSF_EINVAL, "priors[%d] = %g is not in (0, 1)", v, p);
     l64[v] = log((1.0 - p) / p);
     l32[v] = (float)l64[v];
+  }
+  if (!c->priors.empty()) {
+    int rc = drain_stream(stream);
+    if (rc) return rc;
   }
   if (c->llr64.ensure(sizeof(double) * (size_t)c->N) || c->llr32.ensure(sizeof(float) * (size_t)c->N))
     return fail(BPSF_ENOMEM, "LLR buffers");
@@ -302,7 +315,7 @@ int update_llr(bpsf_code_s* c, const double* priors)
   return 0;
 }
 
-int update_masks(bpsf_code_s* c, const bpsf_params* p)
+int update_masks(bpsf_code_s* c, const bpsf_params* p, void* stream)
 {
   if (p->cand_mode == BPSF_TRIALS_TABLE) {
     if (p->k > 0 && !c->table) return fail(BPSF_EINVAL, "BPSF_TRIALS_TABLE without a trial table on the code");
@@ -311,6 +324,10 @@ int update_masks(bpsf_code_s* c, const bpsf_params* p)
   const int wm = p->cand_mode == BPSF_TRIALS_WEIGHT_LE ? p->w_max : 0;
   if (c->masks_k == p->k && c->masks_mode == p->cand_mode && c->masks_wmax == wm) return 0;
   std::vector<uint32_t> m = trial_masks(p->k, p->cand_mode, wm);
+  if (c->masks_k >= 0) {
+    int rc = drain_stream(stream);
+    if (rc) return rc;
+  }
   c->n_trials = (int)m.size();
   if (!m.empty()) {
     if (c->masks.ensure(sizeof(uint32_t) * m.size())) return fail(BPSF_ENOMEM, "trial mask table");
@@ -790,9 +807,9 @@ int bpsf_decode(bpsf_code c, const uint8_t* syndromes, const double* priors, int
   if (shots > 0 && (!syndromes || !corrections || !converged || !iterations))
     return fail(BPSF_EINVAL, "NULL buffer");
   std::lock_guard<std::mutex> lk(c->mu);
-  if ((rc = update_llr(c, priors))) return rc;
+  if ((rc = update_llr(c, priors, stream))) return rc;
   if (shots == 0) return 0;
-  if ((rc = update_masks(c, p))) return rc;
+  if ((rc = update_masks(c, p, stream))) return rc;
   Plan pl;
   if ((rc = make_plan(c, p, shots, &pl))) return rc;
   Args& a = pl.args;
@@ -892,7 +909,7 @@ int bpsf_bp_trace(bpsf_code c, const uint8_t* syndrome, const double* priors, co
   bpsf_params q = *p;
   q.k = 0;
   std::lock_guard<std::mutex> lk(c->mu);
-  if ((rc = update_llr(c, priors))) return rc;
+  if ((rc = update_llr(c, priors, nullptr))) return rc;
   Plan pl;
   if ((rc = make_plan(c, &q, 1, &pl))) return rc;
   const size_t rb = q.precision == BPSF_PREC_FP64 ? 8 : 4;
@@ -991,8 +1008,8 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
   for (int i = 0; i < m->n; ++i) {
     bpsf_code_s* c = m->codes[i];
     std::lock_guard<std::mutex> lc(c->mu);
-    if ((rc = update_llr(c, priors[i]))) return rc;
-    if ((rc = update_masks(c, p))) return rc;
+    if ((rc = update_llr(c, priors[i], stream))) return rc;
+    if ((rc = update_masks(c, p, stream))) return rc;
     uniform = uniform && c->uniform;
   }
   if (shots == 0) return 0;
@@ -1228,7 +1245,7 @@ int bpsf_autotune(bpsf_code c, const uint8_t* syndromes, const double* priors, i
       std::lock_guard<std::mutex> lk(c->mu);
       c->tuned_D = ds[i];
       c->tuned_wpc = 0;
-      if ((rc = update_llr(c, priors)) || (rc = update_masks(c, p))) break;
+      if ((rc = update_llr(c, priors, stream)) || (rc = update_masks(c, p, stream))) break;
       Plan pl;
       if ((rc = make_plan(c, p, shots, &pl))) break;
       max_w = pl.grid[MODE_MAIN] / c->cus;

@@ -103,3 +103,35 @@ def test_deterministic_and_batch_independent():
     sh = U.gpu_decode(code.hx, syn[perm], 0.07, prm)
     assert np.array_equal(sh["correction"], full["correction"][perm])
     assert np.array_equal(sh["iterations"], full["iterations"][perm])
+
+
+def test_new_priors_wait_for_queued_decodes():
+    """Two decodes on one handle and one side stream, enqueued back to back
+    with different non-uniform priors: the second call's LLR tables must not
+    reach the first call's kernels. Each result equals the oracle's with its
+    own priors."""
+    import torch
+    from paper_2507_00254_amd import bpsf as B
+    code, _, syn = U.inputs("bb144", 0.05, 8192, tag=14)
+    rng = np.random.default_rng(14)
+    pri = [rng.uniform(0.02, 0.07, code.n), rng.uniform(0.03, 0.09, code.n)]
+    prm = U.oracle_params(k=6)
+    want = [U.oracle_decode(code.hx, syn, x, prm, precision="f32") for x in pri]
+    h = B.bpsf_load_code(code.hx)
+    try:
+        st = torch.cuda.Stream()
+        bp = B.make_params(precision=B.PREC_FP32)
+        with torch.cuda.stream(st):
+            s = torch.from_numpy(syn).cuda()
+            outs = [(torch.empty((len(syn), code.n), dtype=torch.uint8, device="cuda"),
+                     torch.empty((len(syn),), dtype=torch.uint8, device="cuda"),
+                     torch.empty((len(syn),), dtype=torch.int32, device="cuda")) for _ in pri]
+        for x, o in zip(pri, outs):
+            B.bpsf_decode(h, s, x, bp, *o, stream=st)
+        st.synchronize()
+        for o, w in zip(outs, want):
+            got = {"correction": o[0].cpu().numpy(), "converged": o[1].cpu().numpy(), "iterations": o[2].cpu().numpy()}
+            assert len(U.mismatches(got, w)) == 0
+        assert (want[0]["correction"] != want[1]["correction"]).any()   # the priors change the result
+    finally:
+        B.bpsf_free_code(h)
