@@ -540,8 +540,7 @@ def main():
     code = codes.bb144()
     p = args.p
     n = args.shots
-    key = shots.stream_key(shots.MASTER_SEED, 2, code.n, int(round(p * 100000)))
-    _, syn = shots.make_shots(code.hx, p, n, key)
+    _, syn = shots.headline_shots(code.hx, p, n)
     pri = np.full(code.n, p)
     prm = B.make_params(max_iter=100, cand_max_iter=20, k=6, alpha=0.625, precision=B.PREC_FP32)
 

@@ -110,17 +110,28 @@ def test_dem_refuses_unsupported_requests():
 
 def test_dem_logical_error_rate_is_the_oracles():
     """The decoded observables: a shot fails when the residual e + e_hat
-    flips a logical observable or the decoder did not converge; GPU and
-    oracle fail on the same shots."""
+    flips a logical observable or the decoder did not converge. The GPU fails
+    on exactly the shots the float oracle fails on, and its logical error
+    rate lies in the double oracle's Wilson 95% interval on the same shots."""
+    from oracle import oracle as O
     dem = _dem("bb144", 12, 0.003)
-    err, syn, _ = circuit.sample(dem, 400, shots.stream_key(shots.MASTER_SEED, 1405))
+    err, syn, _ = circuit.sample(dem, 1000, shots.stream_key(shots.MASTER_SEED, 1405))
     prm = U.oracle_params(max_iter=100, cand_max_iter=100, k=16, select_mode=1, alpha=0.0)
     masks = trials.sample_trial_list(16, 6, 5, shots.stream_key(shots.MASTER_SEED, 1406))
     g = _decode_table(dem.h, syn, dem.priors, prm, masks)
-    res = (g["correction"] ^ err).astype(np.int64)
-    fail = ((res @ dem.obs.T.astype(np.int64)) & 1).any(axis=1) | (g["converged"] == 0)
-    print(f"logical failures {fail.sum()} / {len(syn)}", flush=True)
-    assert fail.mean() < 0.05
+
+    def fails(r):
+        res = (r["correction"] ^ err).astype(np.int64)
+        return ((res @ dem.obs.T.astype(np.int64)) & 1).any(axis=1) | (r["converged"] == 0)
+
+    o32 = O.bpsf_batch(dem.h, syn, dem.priors, prm, prec="f32", threads=16, masks=masks)
+    o64 = O.bpsf_batch(dem.h, syn, dem.priors, prm, prec="f64", threads=16, masks=masks)
+    fg, f32, f64 = fails(g), fails(o32), fails(o64)
+    lo, hi = U.wilson(int(f64.sum()), len(syn))
+    print(f"logical failures gpu {fg.sum()} float oracle {f32.sum()} double oracle {f64.sum()} / {len(syn)}; "
+          f"interval [{lo:.4f}, {hi:.4f}]", flush=True)
+    assert np.array_equal(fg, f32)
+    assert f64.sum() > 0 and lo <= fg.mean() <= hi
 
 
 def _decode_table64(h, syn, pri, prm, masks):

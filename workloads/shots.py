@@ -76,6 +76,13 @@ def make_shots(h: np.ndarray, p, n_shots: int, key: np.uint64, shot_start: int =
     return errs, syns
 
 
+def headline_shots(h: np.ndarray, p: float, n_shots: int):
+    """The benchmark's shots for check matrix ``h`` at error rate ``p``: stream
+    (master seed, 2, N, p * 10^5). Returns ``(errors, syndromes)``."""
+    key = stream_key(MASTER_SEED, 2, h.shape[1], int(round(p * 100000)))
+    return make_shots(h, p, n_shots, key)
+
+
 def random_syndromes(m: int, n_shots: int, key: np.uint64, density: float = 0.5) -> np.ndarray:
     """Arbitrary (not necessarily feasible-by-low-weight) syndromes, for edge cases."""
     u = uniforms(key, 0, n_shots * m).reshape(n_shots, m)
