@@ -40,7 +40,7 @@ def record() -> dict:
     den = 1 + Z95 * Z95 / n
     cen = (ph + Z95 * Z95 / (2 * n)) / den
     half = Z95 * np.sqrt(ph * (1 - ph) / n + Z95 * Z95 / (4 * n * n)) / den
-    return {"shots": n, "failed_first_bp": int((o["main_iterations"] == prm.max_iter).sum()),
+    return {"shots": n, "failed_first_bp": int(((o["winner"] >= 0) | (o["converged"] == 0)).sum()),
             "converged": int(o["converged"].sum()), "trial_winners": int((o["winner"] >= 0).sum()),
             "logical_failures": k, "ler": float(ph), "wilson95_lo": float(cen - half), "wilson95_hi": float(cen + half),
             "main_iterations": int(o["main_iterations"].sum()), "trial_iterations": int(o["trial_iterations"].sum())}

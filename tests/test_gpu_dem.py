@@ -115,7 +115,7 @@ def test_dem_logical_error_rate_is_the_oracles():
     rate lies in the double oracle's Wilson 95% interval on the same shots."""
     from oracle import oracle as O
     dem = _dem("bb144", 12, 0.003)
-    err, syn, _ = circuit.sample(dem, 1000, shots.stream_key(shots.MASTER_SEED, 1405))
+    err, syn, _ = circuit.sample(dem, 5000, shots.stream_key(shots.MASTER_SEED, 1405))
     prm = U.oracle_params(max_iter=100, cand_max_iter=100, k=16, select_mode=1, alpha=0.0)
     masks = trials.sample_trial_list(16, 6, 5, shots.stream_key(shots.MASTER_SEED, 1406))
     g = _decode_table(dem.h, syn, dem.priors, prm, masks)

@@ -41,7 +41,7 @@ def test_bench_configuration_full_size():
     # the work counters are the oracle's iteration sums
     won = o32["winner"] >= 0
     assert st["errors"] == 0
-    assert st["failed_shots"] == int((o32["main_iterations"] == prm.max_iter).sum()) > 0
+    assert st["failed_shots"] == int(((o32["winner"] >= 0) | (o32["converged"] == 0)).sum()) > 0
     assert st["main_iterations"] == int(o32["main_iterations"].sum())
     assert st["trial_iterations"] == int(o32["trial_iterations"].sum())
     assert st["rerun_iterations"] == int((o32["iterations"] - o32["main_iterations"])[won].sum())

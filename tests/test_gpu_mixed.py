@@ -196,7 +196,7 @@ def test_grouped_call_with_one_code_present():
         got = {"correction": corr.cpu().numpy()[:, :288], "converged": conv.cpu().numpy(), "iterations": it.cpu().numpy()}
         o = U.oracle_decode(h, syn, p, prm, precision="f32")
         assert len(U.mismatches(got, o)) == 0
-        assert st[4]["failed_shots"] == int((o["main_iterations"] == prm.max_iter).sum() or st[4]["failed_shots"])
+        assert st[4]["failed_shots"] == int(((o["winner"] >= 0) | (o["converged"] == 0)).sum())
         assert all(st[c]["main_iterations"] == 0 for c in range(4))
     finally:
         B.bpsf_mix_free(mix)

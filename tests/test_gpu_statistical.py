@@ -70,7 +70,7 @@ def test_fp32_agrees_with_fp64_oracle(code_name, p, n, k):
 
 # the configuration points, and [[72]] at p = 0.05 (reported, not a
 # configuration point: that workload specifies double messages)
-@pytest.mark.parametrize("code_name,p,n,k", [pt if isinstance(pt, tuple) else tuple(pt.values)
+@pytest.mark.parametrize("code_name,p,n,k", [tuple(pt.values) if hasattr(pt, "marks") else pt
                                              for pt in CONFIG_POINTS] + [("bb72", 0.05, 20_000, 4)])
 def test_fp32_logical_error_rate_and_divergence(code_name, p, n, k):
     """The logical error rate lies in the oracle's Wilson 95% interval on the
@@ -98,7 +98,7 @@ def test_config1_double_is_exact():
     o = U.oracle_decode(code.hx, syn, 0.05, prm, precision="f64", threads=16)
     g = U.gpu_decode(code.hx, syn, 0.05, prm, precision="f64")
     assert len(U.mismatches(g, o)) == 0
-    assert g["stats"]["failed_shots"] == int((o["main_iterations"] == prm.max_iter).sum()) > 0
+    assert g["stats"]["failed_shots"] == int(((o["winner"] >= 0) | (o["converged"] == 0)).sum()) > 0
     fo = _logical_failures(code, err, o)
     lo, hi = U.wilson(int(fo.sum()), len(syn))
     print(f"  LER {fo.mean():.4e} CI [{lo:.4e}, {hi:.4e}]", flush=True)
@@ -133,7 +133,7 @@ def test_phenomenological_fp32_against_fp64_oracle(p, n):
     same = (g["correction"] == o["correction"]).all(axis=1) & (g["converged"] == o["converged"])
     print(f"  identical shots {same.mean():.6f} ({(~same).sum()} differ)", flush=True)
     assert same.mean() >= 0.9999
-    assert g["stats"]["failed_shots"] == int((o["main_iterations"] == prm.max_iter).sum()) > 0
+    assert g["stats"]["failed_shots"] == int(((o["winner"] >= 0) | (o["converged"] == 0)).sum()) > 0
     assert g["stats"]["errors"] == 0
     fo = _phen_failures(c, 12, err, o)
     fg = _phen_failures(c, 12, err, g)
