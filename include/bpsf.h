@@ -151,6 +151,28 @@ int bpsf_decode(bpsf_code code, const uint8_t* syndromes, const double* priors, 
                 void* stream);
 
 /*
+ * bpsf_decode for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, results and work counters as bpsf_decode, but the call's
+ * scratch (work counters, one 64-bit trial key and one failure record per
+ * shot) lives in a fixed array of 32 MiB that the library holds on every
+ * device it runs on until the process ends, and the call allocates nothing
+ * (the code's own tables are sized when it is loaded). The current device
+ * must be the code's. Calls needing more scratch than the array holds
+ * (8 + 4 * record words bytes per shot, e.g. 272 bytes per shot of
+ * [[144,12,12]] with |Phi| = 6 in large calls, 944 bytes in calls of at most
+ * 8192 shots, which run a kernel family with longer records) fail with
+ * BPSF_EINVAL and enqueue nothing. Every such call on one device shares
+ * that device's array: calls whose work overlaps on the device (other
+ * streams, other threads, other handles) race and must be ordered by the
+ * caller; bpsf_last_stats reports the last call's counters until the next
+ * such call on the device.
+ */
+int bpsf_decode_noalloc(bpsf_code code, const uint8_t* syndromes, const double* priors, int64_t shots,
+                        const bpsf_params* params, uint8_t* corrections, uint8_t* converged, int32_t* iterations,
+                        void* stream);
+
+/*
  * Grow the handle's scratch now for calls of up to `shots` shots with these
  * parameters (their k and the launch shape set the record size; every shape
  * a call of up to `shots` shots can take is covered, the small family's

@@ -68,6 +68,7 @@ def _load():
     lib.bpsf_free_code.argtypes = [vp]
     lib.bpsf_free_code.restype = None
     lib.bpsf_decode.argtypes = [vp, vp, P(C.c_double), i64, P(bpsf_params), vp, vp, vp, vp]
+    lib.bpsf_decode_noalloc.argtypes = [vp, vp, P(C.c_double), i64, P(bpsf_params), vp, vp, vp, vp]
     lib.bpsf_last_stats.argtypes = [vp, vp, P(bpsf_stats)]
     lib.bpsf_bp_trace.argtypes = [vp, P(C.c_uint8), P(C.c_double), P(bpsf_params), vp, vp, P(C.c_uint8),
                                   P(i32), P(C.c_uint8)]
@@ -205,12 +206,13 @@ def _on_device(*ts):
 
 
 def bpsf_decode(handle, syndromes, priors, params: bpsf_params, corrections, converged, iterations,
-                stream=None) -> None:
+                stream=None, noalloc: bool = False) -> None:
     """Enqueue a decode. ``syndromes`` uint8 [shots, M], ``corrections`` uint8
     [shots, N], ``converged`` uint8 [shots], ``iterations`` int32 [shots] are
     torch tensors on the GPU; ``priors`` is a host array of N probabilities.
     Shapes and element types are checked here (the library takes rows of M
-    and N bytes)."""
+    and N bytes). ``noalloc`` calls bpsf_decode_noalloc (scratch in the
+    library's fixed device array, no allocation)."""
     import torch
     info = bpsf_code_info(handle)
     m, n = info["M"], info["N"]
@@ -221,7 +223,8 @@ def bpsf_decode(handle, syndromes, priors, params: bpsf_params, corrections, con
     _outputs(corrections, converged, iterations, shots, n, exact_n=n)
     pri = _priors_of(priors, n)
     _on_device(syndromes, corrections, converged, iterations)
-    _check(LIB.bpsf_decode(C.c_void_p(handle), C.c_void_p(syndromes.data_ptr()),
+    fn = LIB.bpsf_decode_noalloc if noalloc else LIB.bpsf_decode
+    _check(fn(C.c_void_p(handle), C.c_void_p(syndromes.data_ptr()),
                            pri.ctypes.data_as(C.POINTER(C.c_double)), shots, C.byref(params),
                            C.c_void_p(corrections.data_ptr()), C.c_void_p(converged.data_ptr()),
                            C.c_void_p(iterations.data_ptr()), _stream_ptr(stream)))

@@ -105,6 +105,7 @@ struct bpsf_code_s {
   DevBuf masks;
   // scratch
   DevBuf records, keys, counters;
+  unsigned long long* last_counters = nullptr;   // counters of the last decode call (its scratch)
   int tuned_D = 0;            // decodes per wave (0: the most that fit)
   int tuned_wpc = 0;          // resident waves per CU of the persistent grids (0: as many as fit)
   // optional per-phase timing: events[i] marks the boundary before phase i
@@ -432,7 +433,16 @@ int fill_code_args(const bpsf_code_s* c, const bpsf_params* p, const TileDesc& t
   return 0;
 }
 
-int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
+// Scratch of a call carved out of a fixed region of `bytes` bytes at `base`
+// (256-byte aligned): counters, then keys, then records.
+struct FixedScratch {
+  void* base = nullptr;
+  size_t bytes = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl, const FixedScratch* fixed = nullptr)
 {
   const bool layered = (p->flags & BPSF_FLAG_LAYERED) != 0;
   if (layered && (c->wide >= 0 || c->sparse >= 0 || c->n_layers < 1))
@@ -455,14 +465,26 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl)
   if (t.D > 0 && shots <= SMALL_CHUNK_SHOTS_PER_D * t.D) a.chunk = t.D;
   // scratch: one record and key per shot at most
   const int64_t cap = shots > 0 ? shots : 1;
-  if (c->records.ensure(sizeof(int32_t) * (size_t)a.rec_stride * (size_t)cap) ||
-      c->keys.ensure(sizeof(unsigned long long) * (size_t)cap) ||
-      c->counters.ensure(sizeof(unsigned long long) * CNT_WORDS))
-    return fail(BPSF_ENOMEM, "scratch for %lld shots", (long long)shots);
-  a.records = static_cast<int32_t*>(c->records.p);
+  const size_t rec_bytes = sizeof(int32_t) * (size_t)a.rec_stride * (size_t)cap;
+  const size_t key_bytes = sizeof(unsigned long long) * (size_t)cap;
+  const size_t cnt_bytes = sizeof(unsigned long long) * CNT_WORDS;
+  if (fixed) {
+    const size_t need = align256(cnt_bytes) + align256(key_bytes) + rec_bytes;
+    if (need > fixed->bytes)
+      return fail(BPSF_EINVAL, "%lld shots need %zu bytes of scratch; the fixed scratch holds %zu", (long long)shots,
+                  need, fixed->bytes);
+    unsigned char* b = static_cast<unsigned char*>(fixed->base);
+    a.counters = reinterpret_cast<unsigned long long*>(b);
+    a.keys = reinterpret_cast<unsigned long long*>(b + align256(cnt_bytes));
+    a.records = reinterpret_cast<int32_t*>(b + align256(cnt_bytes) + align256(key_bytes));
+  } else {
+    if (c->records.ensure(rec_bytes) || c->keys.ensure(key_bytes) || c->counters.ensure(cnt_bytes))
+      return fail(BPSF_ENOMEM, "scratch for %lld shots", (long long)shots);
+    a.records = static_cast<int32_t*>(c->records.p);
+    a.keys = static_cast<unsigned long long*>(c->keys.p);
+    a.counters = static_cast<unsigned long long*>(c->counters.p);
+  }
   a.rec_cap = cap;
-  a.keys = static_cast<unsigned long long*>(c->keys.p);
-  a.counters = static_cast<unsigned long long*>(c->counters.p);
   const bool fp64 = p->precision == BPSF_PREC_FP64;
   if (c->sparse >= 0) {
     const SparseDesc d = sparse_desc(c->sparse);
@@ -771,6 +793,18 @@ int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, in
              hipMemcpy(c->ell16.p, ell16.data(), ell16.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
       rc = fail(BPSF_EDEVICE, "uploading layer tables");
   }
+  // per-call tables at their largest size now, so that no decode call has
+  // to allocate them: channel LLRs, the initial messages of a wide code, the
+  // largest generated trial list (2^16 masks)
+  if (!rc && (c->llr64.ensure(sizeof(double) * (size_t)N) || c->llr32.ensure(sizeof(float) * (size_t)N) ||
+              c->masks.ensure(sizeof(uint32_t) * ((size_t)1 << 16))))
+    rc = fail(BPSF_ENOMEM, "LLR and trial tables");
+  if (!rc && c->wide >= 0) {
+    const WideDesc d = wide_desc(c->wide);
+    const size_t n = (size_t)c->W * 64 * d.NW * d.IC;
+    if (c->init64.ensure(sizeof(double) * n) || c->init32.ensure(sizeof(float) * n))
+      rc = fail(BPSF_ENOMEM, "initial message tables");
+  }
   if (rc) { delete c; return rc; }
   if (c->wide >= 0) c->ell_host = std::move(ell);
   *out = c;
@@ -795,9 +829,15 @@ int bpsf_code_info(bpsf_code c, int32_t* M, int32_t* N, int32_t* edges, int32_t*
   return 0;
 }
 
-int bpsf_decode(bpsf_code c, const uint8_t* syndromes, const double* priors, int64_t shots,
-                const bpsf_params* p, uint8_t* corrections, uint8_t* converged, int32_t* iterations,
-                void* stream)
+}  // extern "C"
+
+namespace {
+
+// One decode call: the three phases of Algorithm 1 as stream-ordered launches,
+// with the handle's scratch (fixed == NULL) or a fixed region.
+int decode_call(bpsf_code c, const uint8_t* syndromes, const double* priors, int64_t shots, const bpsf_params* p,
+                uint8_t* corrections, uint8_t* converged, int32_t* iterations, void* stream,
+                const FixedScratch* fixed)
 {
   if (!c) return fail(BPSF_EINVAL, "code is NULL");
   int rc = check_params(p);
@@ -811,7 +851,7 @@ int bpsf_decode(bpsf_code c, const uint8_t* syndromes, const double* priors, int
   if (shots == 0) return 0;
   if ((rc = update_masks(c, p, stream))) return rc;
   Plan pl;
-  if ((rc = make_plan(c, p, shots, &pl))) return rc;
+  if ((rc = make_plan(c, p, shots, &pl, fixed))) return rc;
   Args& a = pl.args;
   a.syndromes = syndromes;
   a.corrections = corrections;
@@ -819,6 +859,7 @@ int bpsf_decode(bpsf_code c, const uint8_t* syndromes, const double* priors, int
   a.iterations = iterations;
   const bool fp64 = p->precision == BPSF_PREC_FP64;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  c->last_counters = a.counters;
   if (reset_counters(a.counters, CNT_WORDS, stream)) return fail(BPSF_EDEVICE, "counter reset launch");
   auto launch = [&](int mode) {
     // no more workgroups than the phase can have tasks (one decode per
@@ -845,6 +886,60 @@ int bpsf_decode(bpsf_code c, const uint8_t* syndromes, const double* priors, int
   c->timed_last = c->timing;
   c->timed_phases = p->k > 0 ? 3 : 1;
   return 0;
+}
+
+// The fixed scratch of bpsf_decode_noalloc: one copy per device, held until
+// the process ends. Host code never uses the array's name as an address: it
+// asks the runtime for each device's copy once (with that device current)
+// and passes that address to the kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;   // device -> its copy of `scratch`
+
+int scratch_address(int dev, void** out)
+{
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return 0;
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(BPSF_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  g_scratch_addr[dev] = ptr;
+  *out = ptr;
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bpsf_decode(bpsf_code c, const uint8_t* syndromes, const double* priors, int64_t shots,
+                const bpsf_params* p, uint8_t* corrections, uint8_t* converged, int32_t* iterations,
+                void* stream)
+{
+  return decode_call(c, syndromes, priors, shots, p, corrections, converged, iterations, stream, nullptr);
+}
+
+int bpsf_decode_noalloc(bpsf_code c, const uint8_t* syndromes, const double* priors, int64_t shots,
+                        const bpsf_params* p, uint8_t* corrections, uint8_t* converged, int32_t* iterations,
+                        void* stream)
+{
+  if (!c) return fail(BPSF_EINVAL, "code is NULL");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(BPSF_EDEVICE, "hipGetDevice");
+  if (dev != c->device)
+    return fail(BPSF_EINVAL, "the current device (%d) is not the code's device (%d)", dev, c->device);
+  FixedScratch fx;
+  int rc = scratch_address(dev, &fx.base);
+  if (rc) return rc;
+  fx.bytes = NOALLOC_SCRATCH_BYTES;
+  return decode_call(c, syndromes, priors, shots, p, corrections, converged, iterations, stream, &fx);
 }
 
 int bpsf_set_timing(bpsf_code c, int enable)
@@ -874,10 +969,10 @@ int bpsf_last_stats(bpsf_code c, void* stream, bpsf_stats* out)
 {
   if (!c || !out) return fail(BPSF_EINVAL, "NULL argument");
   memset(out, 0, sizeof *out);
-  if (!c->counters.p) return 0;
+  if (!c->last_counters) return 0;
   unsigned long long h[CNT_WORDS];
   HIP_OK(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
-  HIP_OK(hipMemcpy(h, c->counters.p, sizeof h, hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(h, c->last_counters, sizeof h, hipMemcpyDeviceToHost));
   out->main_iterations = (int64_t)h[ST_MAIN_ITERS];
   out->trial_iterations = (int64_t)h[ST_CAND_ITERS];
   out->rerun_iterations = (int64_t)h[ST_EMIT_ITERS];
