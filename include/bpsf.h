@@ -89,7 +89,11 @@ typedef struct {
 
 typedef struct {
   int64_t main_iterations;   /* first-BP iterations summed over the shots of the last call */
-  int64_t trial_iterations;  /* trial-BP iterations summed over every trial run */
+  int64_t trial_iterations;  /* trial-BP iterations summed over every trial run; with
+                                BPSF_TRIALS_ALL_SUBSETS the empty trial of a failed shot is
+                                not run (it would repeat the first cand_max_iter iterations of
+                                the failed first BP) unless FORCE_PP or NO_EARLY_STOP is set
+                                or cand_max_iter > max_iter */
   int64_t rerun_iterations;  /* iterations of the re-runs that emit winning trials */
   int64_t failed_shots;      /* shots whose first BP failed (or all shots with FORCE_PP, k > 0) */
   int64_t converged_trials;  /* trials that reproduced their syndrome */

@@ -378,6 +378,15 @@ struct Plan {
   int grid[3];
 };
 
+// Whether a call leaves out the empty trial: all subsets of Phi, trials only
+// after a failed first BP (no FORCE_PP), a stop at the first success of a run
+// (no NO_EARLY_STOP), and trials no longer than the first BP.
+bool empty_trial_skipped(const bpsf_params* p)
+{
+  return p->cand_mode == BPSF_TRIALS_ALL_SUBSETS && p->k > 0 &&
+         !(p->flags & (BPSF_FLAG_FORCE_PP | BPSF_FLAG_NO_EARLY_STOP)) && p->cand_max_iter <= p->max_iter;
+}
+
 // Code, geometry and parameter fields of a launch's Args (no problem
 // buffers, no scratch).
 int fill_code_args(const bpsf_code_s* c, const bpsf_params* p, const TileDesc& t, Args* out)
@@ -424,6 +433,15 @@ int fill_code_args(const bpsf_code_s* c, const bpsf_params* p, const TileDesc& t
     a.n_trials = c->n_trials;
     a.trial_masks = static_cast<const uint32_t*>(c->masks.p);
     a.mask_stride = 0;
+    // The empty trial (mask 0, the first of all subsets) decodes s itself
+    // from fresh messages with the first BP's damping schedule: its run is
+    // the first cand_max_iter iterations of the failed first BP, which never
+    // reproduced s, so it cannot succeed. The kernels see the list from the
+    // second mask on (trial indices shift by one, which keeps their order).
+    if (empty_trial_skipped(p)) {
+      a.trial_masks += 1;
+      a.n_trials -= 1;
+    }
   }
   // record: header, s bits per lane, every Phi column's share per lane, Phi
   const int kk = p->k > 0 ? p->k : 1;

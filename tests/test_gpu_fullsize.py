@@ -43,7 +43,8 @@ def test_bench_configuration_full_size():
     assert st["errors"] == 0
     assert st["failed_shots"] == int(((o32["winner"] >= 0) | (o32["converged"] == 0)).sum()) > 0
     assert st["main_iterations"] == int(o32["main_iterations"].sum())
-    assert st["trial_iterations"] == int(o32["trial_iterations"].sum())
+    # the oracle also runs the empty trial of every failed shot (cand_max_iter iterations each)
+    assert st["trial_iterations"] == int(o32["trial_iterations"].sum()) - prm.cand_max_iter * st["failed_shots"]
     assert st["rerun_iterations"] == int((o32["iterations"] - o32["main_iterations"])[won].sum())
     # every shot against the double oracle
     o64 = U.oracle_decode(code.hx, syn, 0.03, prm, precision="f64", threads=16)

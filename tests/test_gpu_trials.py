@@ -32,7 +32,12 @@ def test_generated_list_as_table_matches_generated_mode():
     tab = B.bpsf_num_trials(B.make_params(k=6))
     got = _decode_table(code.hx, syn, 0.05, prm, tab)
     assert len(U.mismatches(got, ref)) == 0
-    assert got["stats"] == ref["stats"]
+    # the generated mode leaves out the empty trial of every failed shot (it
+    # repeats the failed first BP); the caller's list runs it to its cap
+    extra = {"trial_iterations": prm.cand_max_iter * ref["stats"]["failed_shots"]}
+    assert ref["stats"]["failed_shots"] > 0
+    for f, v in ref["stats"].items():
+        assert got["stats"][f] == v + extra.get(f, 0), f
 
 
 @pytest.mark.parametrize("select", [0, 1])
@@ -44,7 +49,6 @@ def test_sampled_lists_match_oracle(select, per_shot):
     key = shots.stream_key(shots.MASTER_SEED, 971)
     masks = trials.sample_trial_table(8, 4, 5, key, n) if per_shot else trials.sample_trial_list(8, 4, 5, key)
     got = _decode_table(code.hx, syn, p, prm, masks)
-    o = U.oracle_decode(code.hx, syn, p, prm, precision="f32") if False else None
     from oracle import oracle as O
     o = O.bpsf_batch(code.hx, syn, p, prm, prec="f32", threads=8, masks=masks)
     bad = U.mismatches(got, o)
