@@ -24,8 +24,59 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 EDGE_BYTES = 16          # one float v2c and one float c2v per edge, each written once and read once
-LDS_PEAK_GBS = 256 * 128 * 2.4   # 256 CUs x 128 B/clk x 2.4 GHz = 78,643 GB/s
+LDS_SPEC_GBS = 256 * 128 * 2.4   # data-sheet figure: 256 CUs x 128 B/clk x 2.4 GHz = 78,643 GB/s
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4 / 1000   # 32-bit VALU lane-ops: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+
+_LDS = {}
+
+
+def lds_peak() -> dict:
+    """The device's LDS bandwidth, measured now by the streaming probe
+    (include/lds_probe.h): every read and write width at a few occupancies;
+    the peak is the largest rate (ds_read_b128 on gfx950)."""
+    if not _LDS:
+        from paper_2507_00254_amd import lds_probe
+        m = lds_probe.measure()
+        rate = {(r["kind"], r["width"]): max(x["GBps"] for x in m["rows"]
+                                             if (x["kind"], x["width"]) == (r["kind"], r["width"]))
+                for r in m["rows"]}
+        # the roof of the decoder's own access mix: one 4-byte read and one
+        # 4-byte write per message, reads and writes sharing the LDS
+        mix = 2.0 / (1.0 / rate[("read", 4)] + 1.0 / rate[("write", 4)])
+        _LDS.update({"peak": m["peak_GBps"], "peak_at": m["peak_at"], "b32_read_write_mix": mix,
+                     "rates_GBps": {f"{k}_b{8 * w}": round(v, 1) for (k, w), v in sorted(rate.items())}})
+    return _LDS
+
+
+def lds_roofline(kernel: str, achieved: float, per_unit: str, traffic=None) -> dict:
+    """The roofline object of an LDS-bound kernel against the measured peak."""
+    L = lds_peak()
+    return {"bound": "lds", "kernel": kernel, "achieved": achieved, "peak": L["peak"], "unit": "GB/s",
+            "frac": achieved / L["peak"], "traffic": traffic, "per_unit": per_unit,
+            "peak_source": f"measured this run: {L['peak_at']['kind']} b{8 * L['peak_at']['width']} streaming "
+                           f"probe (liblds_probe.so)",
+            "spec_peak": LDS_SPEC_GBS, "frac_of_spec": achieved / LDS_SPEC_GBS,
+            "b32_read_write_mix_peak": L["b32_read_write_mix"],
+            "frac_of_b32_mix": achieved / L["b32_read_write_mix"], "probe_GBps": L["rates_GBps"]}
+
+
+def valu_from_profile(phase: str, ms: float):
+    """VALU lane-op rate of a phase: SQ_INSTS_VALU per dispatch from the
+    committed counter summary (when it was taken on the current kernel
+    source, else None) x 64 lanes over the phase's live mean duration."""
+    path = os.path.join(ROOT, "profiles", "counters_bb144_p003.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_src_sha") != kernel_hash():
+        return None
+    insts = rec.get("phases", {}).get(phase, {}).get("SQ_INSTS_VALU")
+    if not insts:
+        return None
+    tops = 64.0 * insts / (ms * 1e-3) / 1e12
+    return {"lane_ops_per_dispatch": 64.0 * insts, "achieved_Tops": tops, "peak_Tops": VALU_PEAK_TOPS,
+            "frac": tops / VALU_PEAK_TOPS, "source": "SQ_INSTS_VALU, profiles/counters_bb144_p003.json"}
 KERNEL_SOURCES = ("paper_2507_00254_amd/csrc/bpsf_kernels.hip", "paper_2507_00254_amd/csrc/bpsf_tiles.h",
                   "paper_2507_00254_amd/csrc/bpsf_internal.h")
 
@@ -90,6 +141,27 @@ def _pmc_per_dispatch(csv_path: str, counter: str):
     return {ph: acc[ph] / len(seen[ph]) for ph in acc}
 
 
+def counter_summary(csv_paths, out_path):
+    """Per-dispatch mean of every counter in rocprofv3 --pmc CSVs, by decode
+    phase, stamped with the kernel source hash (bench.py reads
+    SQ_INSTS_VALU from it for the VALU fraction)."""
+    import csv
+    names = set()
+    for path in csv_paths:
+        with open(path) as f:
+            names.update(r["Counter_Name"] for r in csv.DictReader(f))
+    rec = {"kernel_src_sha": kernel_hash(), "phases": {}}
+    for name in sorted(names):
+        for path in csv_paths:
+            per = _pmc_per_dispatch(path, name)
+            for ph, v in per.items():
+                if ph != "copy":
+                    rec["phases"].setdefault(ph, {})[name] = v
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec), flush=True)
+
+
 def traffic_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, out_path):
     """Per-dispatch HBM bytes of every phase from two counter runs, scaled by
     what the same counters read for a plain copy of COPY_BYTES."""
@@ -112,19 +184,51 @@ def traffic_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, out_pa
     print(json.dumps(rec), flush=True)
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_share() -> int:
+    """Threads the oracle may use: the host's CPU share for this job (the
+    OMP_NUM_THREADS it sets), else the cores this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    if env and env.isdigit() and int(env) > 0:
+        return min(int(env), aff)
+    return aff
+
+
 def cpu_baseline(h, syn, p, prm, seconds: float):
+    """The double-precision oracle on the host over the first shots of the
+    same workload: one thread for about a third of `seconds`, then the
+    host's CPU share for the rest (static shot partition)."""
     from oracle.oracle import OracleLib
-    threads = min(os.cpu_count() or 1, 16)
     O = OracleLib()
-    done, t0 = 0, time.perf_counter()
-    chunk = 20000
-    while time.perf_counter() - t0 < seconds and done < len(syn):
-        O.bpsf_batch(h, syn[done:done + chunk], p, prm, prec="f64", threads=threads)
-        done += min(chunk, len(syn) - done)
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "shots/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {done} shots of the same workload, double-precision oracle, "
-                      f"{threads} threads, {dt:.1f} s"}
+    share = _cpu_share()
+
+    def leg(threads, budget):
+        done, t0 = 0, time.perf_counter()
+        chunk = 4000 * threads
+        while time.perf_counter() - t0 < budget and done < len(syn):
+            O.bpsf_batch(h, syn[done:done + chunk], p, prm, prec="f64", threads=threads)
+            done += min(chunk, len(syn) - done)
+        return done, time.perf_counter() - t0
+
+    n1, t1 = leg(1, seconds / 3.0)
+    n, t = leg(share, seconds * 2.0 / 3.0)
+    return {"value": n / t, "unit": "shots/s", "cores": share, "kind": "oracle",
+            "sample": f"first {n} shots of the same workload, double-precision oracle, {share} threads, {t:.1f} s",
+            "single_thread": {"value": n1 / t1, "shots": n1, "seconds": t1},
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 MIXED_NAMES = ("bb72", "bb90", "bb108", "bb144", "bb288")
@@ -199,8 +303,8 @@ def run_mixed(args):
                    "max_iter": 100, "k": 6, "trials": 64, "trial_iter": 20, "alpha": 0.625},
         "separate_calls": {"ms_per_step": ms_sep, "value": n / (ms_sep * 1e-3)},
         "speedup_vs_separate": ms_sep / ms_mix,
-        "whole_call_lds_equiv": {"achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                                 "frac": lds_gbs / LDS_PEAK_GBS},
+        "whole_call_lds_equiv": {"achieved": lds_gbs, "peak": lds_peak()["peak"], "unit": "GB/s",
+                                 "frac": lds_gbs / lds_peak()["peak"]},
         "per_code": [{"code": MIXED_NAMES[c], **st[c]} for c in range(len(hs))],
         "invalid_shots": bad,
     }
@@ -257,10 +361,8 @@ def run_phen(args):
         rows.append({"p": p, "shots": n, "ms_per_step": ms, "value": n / (ms * 1e-3), "phases_ms": avg,
                      "work": {**iters, "failed_shots": st["failed_shots"], "errors": st["errors"],
                               "converged_rate": float(conv.float().mean().item())},
-                     "roofline": {"bound": "lds", "kernel": dom, "achieved": ach, "peak": LDS_PEAK_GBS,
-                                  "unit": "GB/s", "frac": ach / LDS_PEAK_GBS,
-                                  "per_unit": f"{EDGE_BYTES} B per edge-iteration x {edges} edges x {iters[dom]} "
-                                              f"iterations"}})
+                     "roofline": lds_roofline(dom, ach, f"{EDGE_BYTES} B per edge-iteration x {edges} edges x "
+                                                        f"{iters[dom]} iterations")})
         print(json.dumps(rows[-1]), flush=True)
     B.bpsf_free_code(handle)
     print(json.dumps({"metric": "decoded shots/s, phenomenological [[144,12,12]] over 12 rounds (864 x 2592)",
@@ -367,10 +469,8 @@ def run_dem(args):
                      "syndrome_latency_us": {"calls": int(len(lat)), "mean": float(lat.mean()),
                                              "p50": float(np.percentile(lat, 50)),
                                              "p99": float(np.percentile(lat, 99)), "max": float(lat.max())},
-                     "roofline": {"bound": "lds", "kernel": dom, "achieved": ach, "peak": LDS_PEAK_GBS,
-                                  "unit": "GB/s", "frac": ach / LDS_PEAK_GBS,
-                                  "per_unit": f"{EDGE_BYTES} B per edge-iteration x {edges} edges x {iters[dom]} "
-                                              f"iterations"}})
+                     "roofline": lds_roofline(dom, ach, f"{EDGE_BYTES} B per edge-iteration x {edges} edges x "
+                                                        f"{iters[dom]} iterations")})
         print(json.dumps(rows[-1]), flush=True)
         B.bpsf_free_code(handle)
     print(json.dumps({"metric": "decoded shots/s, circuit-level detector error models of [[144,12,12]] (d = 12 "
@@ -485,7 +585,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--shots", type=int, default=1_000_000)
     ap.add_argument("--p", type=float, default=0.03)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=18.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-calls", type=int, default=200)
     ap.add_argument("--workload", choices=("bb144", "mixed5", "serve", "phen", "dem", "layered"), default="bb144",
@@ -505,7 +605,12 @@ def main():
     ap.add_argument("--traffic-summary", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
                                                            "COPY_WRITE_CSV", "OUT_JSON"),
                     help="write the per-phase HBM traffic summary from rocprofv3 counter CSVs")
+    ap.add_argument("--counter-summary", nargs="+", metavar="CSV_THEN_OUT_JSON",
+                    help="write the per-phase counter summary from rocprofv3 --pmc CSVs (last argument: output)")
     args = ap.parse_args()
+    if args.counter_summary:
+        counter_summary(args.counter_summary[:-1], args.counter_summary[-1])
+        return
     if args.traffic_summary:
         traffic_summary(*args.traffic_summary)
         return
@@ -617,9 +722,9 @@ def main():
                     "p99_us": float(np.percentile(lat, 99)), "max_us": float(np.max(lat))},
         "phases_ms": avg_ms,
         "work": {"edges": edges, **iters, "failed_shots": st["failed_shots"], "converged_rate": conv_rate},
-        "roofline": {"bound": "lds", "kernel": dom, "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / LDS_PEAK_GBS, "traffic": traffic,
-                     "per_unit": f"{EDGE_BYTES} B per edge-iteration x {edges} edges x {iters[dom]} iterations"},
+        "roofline": lds_roofline(dom, achieved, f"{EDGE_BYTES} B per edge-iteration x {edges} edges x "
+                                                f"{iters[dom]} iterations", traffic),
+        "valu": valu_from_profile(dom, avg_ms[dom]),
         "kernel_src_sha": kernel_hash(),
     }
     total_edge_iters = edges * sum(iters.values())
