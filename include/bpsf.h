@@ -310,20 +310,35 @@ int bpsf_autotune(bpsf_code code, const uint8_t* syndromes, const double* priors
                   const bpsf_params* params, int32_t reps, void* stream, bpsf_tuning* out);
 
 /*
- * Request loop. A server decodes requests (a batch of 1..max_batch_shots host
- * syndromes of one of its codes) as they arrive, on a worker thread of its
- * own. Codes (up to 8, one kernel family when batching), their priors
- * (host double [N] each, copied) and the parameters are fixed at creation.
+ * Request loop (the serving counterpart of the paper's parallel CPU
+ * implementation, Section VI, which feeds syndromes through input and output
+ * queues). A server decodes requests (a batch of host syndromes of one of
+ * its codes) as they arrive, on a worker thread of its own. Codes (up to 8,
+ * one kernel family when batching), their priors (host double [N] each,
+ * copied) and the parameters are fixed at creation.
+ *
+ * Device memory: one pool per server of device_budget_bytes (0: half the
+ * device memory free at creation as reported by hipMemGetInfo, at most what
+ * every lane needs for a batch of max_batch_shots), allocated at creation.
+ * A batch of n shots takes a region of n * (max M + max N + 5) bytes (plus
+ * alignment) and, when batching, the scratch of its decode; the region
+ * returns to the pool when the batch completes. A request fails at submit
+ * (BPSF_EINVAL) only when it is larger than max_batch_shots or than the
+ * whole pool can hold (bpsf_server_memory reports that size); otherwise it
+ * waits until a lane and enough pool memory are free.
  *   batching = 1: continuous batching over `lanes` (1..8) streams. Whenever a
- *     lane is free, every waiting request that fits in max_batch_shots is
- *     admitted into one batch: copied to the device grouped by code,
- *     decoded by one bpsf_mix_decode_grouped, copied back. Requests that arrive while batches run
- *     wait for the next free lane, so batches overlap on the device. Device
- *     memory per lane: max_batch_shots * (max M + max N + 5) bytes plus
- *     its mix scratch; pinned host memory per lane: the same staging.
+ *     lane is free, the waiting requests, in arrival order, that fit in
+ *     max_batch_shots and in a free region of the pool are admitted into
+ *     one batch: copied to the device grouped by code, decoded by one mixed
+ *     decode (as bpsf_mix_decode_grouped), copied back in one transfer.
+ *     Requests that arrive while batches run wait for the next free lane,
+ *     so batches overlap on the device.
  *   batching = 0: each request decoded alone with bpsf_decode on its code,
  *     in arrival order, one at a time (lanes must be 1): the per-request form.
- * Results are what bpsf_decode returns for each shot alone.
+ * Pinned host memory per lane: max_batch_shots * (max M + max N + 5) bytes.
+ * Creation runs every kernel shape the server can launch once, on zero
+ * syndromes (first launches load code and would add milliseconds to a
+ * request). Results are what bpsf_decode returns for each shot alone.
  * bpsf_server_submit enqueues a request (host syndromes uint8 [n][M of the
  * code]; outputs host corrections uint8 [n][N], converged uint8 [n],
  * iterations int32 [n]; all must stay valid until the request is collected)
@@ -337,14 +352,17 @@ int bpsf_autotune(bpsf_code code, const uint8_t* syndromes, const double* priors
  * flight; once all are done it collects them and writes latency_s[i] =
  * completion - scheduled arrival and *wall_s (may be NULL) = the time from
  * the start to the last completion. bpsf_server_counters reports batches
- * launched, shots they held and requests completed. bpsf_server_destroy
- * finishes the queued work and frees the server; it returns the first error
- * the worker met, if any.
+ * launched, shots they held and requests completed. bpsf_server_memory
+ * reports the pool size, the bytes in use now and at most since creation
+ * (warm-up excluded), the largest request the pool can hold, and how many
+ * requests had to wait for pool memory (host outs, any may be NULL).
+ * bpsf_server_destroy finishes the queued work and frees the server; it
+ * returns the first error the worker met, if any.
  */
 typedef struct bpsf_server_s* bpsf_server;
 int bpsf_server_create(const bpsf_code* codes, int32_t n_codes, const double* const* priors,
                        const bpsf_params* params, int32_t lanes, int64_t max_batch_shots, int32_t batching,
-                       bpsf_server* out);
+                       int64_t device_budget_bytes, bpsf_server* out);
 int bpsf_server_submit(bpsf_server server, int32_t code, const uint8_t* syndromes, int32_t n,
                        uint8_t* corrections, uint8_t* converged, int32_t* iterations, int64_t* id_out);
 int bpsf_server_wait(bpsf_server server, int64_t id, double* latency_s_out);
@@ -354,6 +372,8 @@ int bpsf_server_replay(bpsf_server server, int64_t n_requests, const double* arr
                        uint8_t* const* converged, int32_t* const* iterations, double* latency_s,
                        double* wall_s);
 int bpsf_server_counters(bpsf_server server, int64_t* batches, int64_t* batch_shots, int64_t* requests_done);
+int bpsf_server_memory(bpsf_server server, int64_t* budget, int64_t* in_use, int64_t* peak, int64_t* max_request,
+                       int64_t* waited_for_memory);
 int bpsf_server_destroy(bpsf_server server);
 
 /*

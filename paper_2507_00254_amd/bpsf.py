@@ -85,7 +85,8 @@ def _load():
     lib.bpsf_set_tile.argtypes = [vp, i32, i32]
     lib.bpsf_autotune.argtypes = [vp, vp, P(C.c_double), i64, P(bpsf_params), i32, vp, P(bpsf_tuning)]
     lib.bpsf_mix_create.argtypes = [P(vp), i32, P(vp)]
-    lib.bpsf_server_create.argtypes = [P(vp), i32, P(P(C.c_double)), P(bpsf_params), i32, i64, i32, P(vp)]
+    lib.bpsf_server_create.argtypes = [P(vp), i32, P(P(C.c_double)), P(bpsf_params), i32, i64, i32, i64, P(vp)]
+    lib.bpsf_server_memory.argtypes = [vp, P(i64), P(i64), P(i64), P(i64), P(i64)]
     lib.bpsf_server_submit.argtypes = [vp, i32, vp, i32, vp, vp, vp, P(i64)]
     lib.bpsf_server_wait.argtypes = [vp, i64, P(C.c_double)]
     lib.bpsf_server_poll.argtypes = [vp, P(i64), i64]
@@ -397,7 +398,7 @@ class Server:
     buffers are numpy arrays; they are kept alive until collected."""
 
     def __init__(self, handles, priors, params: bpsf_params, lanes: int = 2, max_batch_shots: int = 65536,
-                 batching: bool = True):
+                 batching: bool = True, device_budget_bytes: int = 0):
         self._pri = [np.ascontiguousarray(x, dtype=np.float64) for x in priors]
         parr = (C.POINTER(C.c_double) * len(self._pri))(*[x.ctypes.data_as(C.POINTER(C.c_double))
                                                           for x in self._pri])
@@ -409,7 +410,7 @@ class Server:
         for c, (x, (_, n)) in enumerate(zip(self._pri, self._shapes)):
             _priors_of(x, n, f"priors[{c}]")
         _check(LIB.bpsf_server_create(arr, len(handles), parr, C.byref(params), int(lanes), int(max_batch_shots),
-                                      int(bool(batching)), C.byref(out)))
+                                      int(bool(batching)), int(device_budget_bytes), C.byref(out)))
         self.h = out.value
         self._live = {}
 
@@ -471,6 +472,13 @@ class Server:
         v = [C.c_int64() for _ in range(3)]
         _check(LIB.bpsf_server_counters(C.c_void_p(self.h), *[C.byref(x) for x in v]))
         return dict(zip(("batches", "batch_shots", "requests_done"), (x.value for x in v)))
+
+    def memory(self) -> dict:
+        """Device pool: size, bytes in use now and at most, the largest
+        request it holds, and the requests that waited for memory."""
+        v = [C.c_int64() for _ in range(5)]
+        _check(LIB.bpsf_server_memory(C.c_void_p(self.h), *[C.byref(x) for x in v]))
+        return dict(zip(("budget", "in_use", "peak", "max_request", "waited_for_memory"), (x.value for x in v)))
 
     def close(self):
         if self.h:

@@ -558,6 +558,7 @@ struct bpsf_mix_s {
   DevBuf rec_lists;  // [n][shots] int32 record indices of each code
   DevBuf records, keys;
   DevBuf counters;   // [n][CNT_WORDS] per code, then the mix words below
+  unsigned long long* last_counters = nullptr;   // counters of the last call (its scratch)
   std::mutex mu;
 };
 
@@ -1094,9 +1095,38 @@ namespace {
 
 // Shots of the mix either listed by code index (shot_code, device) or
 // grouped: code c's shots are the counts[c] rows after those of codes < c.
+// Record words per shot that cover every tile a mixed call of up to `shots`
+// shots can take (the mixed tile, and the tiles of small or single-code calls).
+int mix_stride_max(bpsf_mix m, int64_t shots, const bpsf_params* p, int* out)
+{
+  int stride = 0, rc = 0;
+  for (int i = 0; i < m->n; ++i) {
+    for (int64_t call : {(int64_t)-1, std::min(shots, SMALL_CALL_SHOTS_PER_D), std::min(shots, SMALL_CALL_SHOTS)}) {
+      TileDesc t;
+      Args a;
+      if (pick_tile(m->codes[i], &t, call)) return fail(BPSF_ENOTSUP, "code %d has no kernel tile", i);
+      if ((rc = fill_code_args(m->codes[i], p, t, &a))) return rc;
+      stride = std::max(stride, a.rec_stride);
+    }
+  }
+  *out = stride;
+  return 0;
+}
+
+// Scratch of a grouped mixed call in a fixed region: counters, keys, the
+// per-code record lists, then the records.
+size_t mix_fixed_bytes(int n_codes, int64_t shots, int stride)
+{
+  const size_t n = (size_t)shots;
+  return align256(sizeof(unsigned long long) * ((size_t)CNT_WORDS * n_codes + MIX_WORDS)) +
+         align256(sizeof(unsigned long long) * n) + align256(sizeof(int32_t) * n * (size_t)n_codes) +
+         sizeof(int32_t) * n * (size_t)stride;
+}
+
 int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, const uint8_t* syndromes,
                int64_t syn_stride, const double* const* priors, int64_t shots, const bpsf_params* p,
-               uint8_t* corrections, int64_t corr_stride, uint8_t* converged, int32_t* iterations, void* stream)
+               uint8_t* corrections, int64_t corr_stride, uint8_t* converged, int32_t* iterations, void* stream,
+               const FixedScratch* fixed = nullptr)
 {
   if (!m) return fail(BPSF_EINVAL, "mix is NULL");
   int rc = check_params(p);
@@ -1173,12 +1203,35 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
   // scratch
   const size_t n = (size_t)shots;
   const size_t words = (size_t)CNT_WORDS * m->n + MIX_WORDS;
-  if ((!counts && m->lists.ensure(sizeof(int32_t) * n * m->n)) || m->rec_lists.ensure(sizeof(int32_t) * n * m->n) ||
-      m->records.ensure(sizeof(int32_t) * n * (size_t)stride) || m->keys.ensure(sizeof(unsigned long long) * n) ||
-      m->counters.ensure(sizeof(unsigned long long) * words))
-    return fail(BPSF_ENOMEM, "scratch for %lld shots", (long long)shots);
-  unsigned long long* cnt = static_cast<unsigned long long*>(m->counters.p);
+  void *lists = nullptr, *rec_lists = nullptr, *records = nullptr, *keys = nullptr, *counters = nullptr;
+  if (fixed) {
+    // grouped calls only (no shot lists)
+    const size_t need = mix_fixed_bytes(m->n, shots, stride);
+    if (counts == nullptr || need > fixed->bytes)
+      return fail(BPSF_EINVAL, "%lld shots need %zu bytes of scratch; the region holds %zu", (long long)shots, need,
+                  fixed->bytes);
+    unsigned char* b = static_cast<unsigned char*>(fixed->base);
+    counters = b;
+    b += align256(sizeof(unsigned long long) * words);
+    keys = b;
+    b += align256(sizeof(unsigned long long) * n);
+    rec_lists = b;
+    b += align256(sizeof(int32_t) * n * (size_t)m->n);
+    records = b;
+  } else {
+    if ((!counts && m->lists.ensure(sizeof(int32_t) * n * m->n)) || m->rec_lists.ensure(sizeof(int32_t) * n * m->n) ||
+        m->records.ensure(sizeof(int32_t) * n * (size_t)stride) || m->keys.ensure(sizeof(unsigned long long) * n) ||
+        m->counters.ensure(sizeof(unsigned long long) * words))
+      return fail(BPSF_ENOMEM, "scratch for %lld shots", (long long)shots);
+    lists = m->lists.p;
+    rec_lists = m->rec_lists.p;
+    records = m->records.p;
+    keys = m->keys.p;
+    counters = m->counters.p;
+  }
+  unsigned long long* cnt = static_cast<unsigned long long*>(counters);
   unsigned long long* mixw = cnt + (size_t)CNT_WORDS * m->n;
+  m->last_counters = cnt;
   int64_t base = 0;
   for (int i = 0; i < m->n; ++i) {
     Args& a = ma.code[i];
@@ -1194,15 +1247,15 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
       a.shot_base = base;
       base += counts[i];
     } else {
-      a.task_shot = static_cast<const int32_t*>(m->lists.p) + (size_t)i * n;
+      a.task_shot = static_cast<const int32_t*>(lists) + (size_t)i * n;
       a.task_count = mixw + MIX_TASKS + i;
     }
-    a.rec_list = static_cast<int32_t*>(m->rec_lists.p) + (size_t)i * n;
+    a.rec_list = static_cast<int32_t*>(rec_lists) + (size_t)i * n;
     a.rec_alloc = mixw + MIX_REC_ALLOC;
-    a.records = static_cast<int32_t*>(m->records.p);
+    a.records = static_cast<int32_t*>(records);
     a.rec_stride = stride;
     a.rec_cap = shots;
-    a.keys = static_cast<unsigned long long*>(m->keys.p);
+    a.keys = static_cast<unsigned long long*>(keys);
     a.counters = cnt + (size_t)CNT_WORDS * i;
   }
   BucketArgs b;
@@ -1210,7 +1263,7 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
   b.shot_code = shot_code;
   b.shots = shots;
   b.n_codes = m->n;
-  b.lists = static_cast<int32_t*>(m->lists.p);
+  b.lists = static_cast<int32_t*>(lists);
   for (int i = 0; i < m->n; ++i) b.counts[i] = mixw + MIX_TASKS + i;
   b.bad = mixw + MIX_BAD;
   if (only >= 0) {
@@ -1283,10 +1336,10 @@ int bpsf_mix_last_stats(bpsf_mix m, void* stream, bpsf_stats* per_code, int64_t*
   std::lock_guard<std::mutex> lk(m->mu);
   for (int i = 0; i < m->n; ++i) memset(&per_code[i], 0, sizeof per_code[i]);
   if (invalid_shots) *invalid_shots = 0;
-  if (!m->counters.p) return 0;
+  if (!m->last_counters) return 0;
   std::vector<unsigned long long> h((size_t)CNT_WORDS * m->n + MIX_WORDS);
   HIP_OK(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
-  HIP_OK(hipMemcpy(h.data(), m->counters.p, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(h.data(), m->last_counters, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost));
   for (int i = 0; i < m->n; ++i) {
     const unsigned long long* w = h.data() + (size_t)CNT_WORDS * i;
     per_code[i].main_iterations = (int64_t)w[ST_MAIN_ITERS];
@@ -1430,16 +1483,7 @@ int bpsf_mix_reserve(bpsf_mix m, int64_t shots, const bpsf_params* p)
   if (p->k > 16) return fail(BPSF_ENOTSUP, "mixed-code calls take |Phi| up to 16");
   std::lock_guard<std::mutex> lk(m->mu);
   int stride = 0;
-  for (int i = 0; i < m->n; ++i) {
-    // the mixed tile, and the tile of a small batch of this code alone
-    for (int64_t call : {(int64_t)-1, std::min(shots, SMALL_CALL_SHOTS_PER_D), std::min(shots, SMALL_CALL_SHOTS)}) {
-      TileDesc t;
-      Args a;
-      if (pick_tile(m->codes[i], &t, call)) return fail(BPSF_ENOTSUP, "code %d has no kernel tile", i);
-      if ((rc = fill_code_args(m->codes[i], p, t, &a))) return rc;
-      stride = std::max(stride, a.rec_stride);
-    }
-  }
+  if ((rc = mix_stride_max(m, shots, p, &stride))) return rc;
   const size_t n = (size_t)shots;
   if (m->lists.ensure(sizeof(int32_t) * n * m->n) || m->rec_lists.ensure(sizeof(int32_t) * n * m->n) ||
       m->records.ensure(sizeof(int32_t) * n * (size_t)stride) || m->keys.ensure(sizeof(unsigned long long) * n) ||
@@ -1486,3 +1530,61 @@ int bpsf_set_trial_table64(bpsf_code c, const uint64_t* masks, int64_t n_trials,
 }
 
 }  // extern "C"
+
+// Library-internal entry points of the request loop (bpsf_internal.h).
+int bpsf::decode_in(bpsf_code c, const uint8_t* syndromes, const double* priors, int64_t shots,
+                    const bpsf_params* p, uint8_t* corrections, uint8_t* converged, int32_t* iterations,
+                    void* stream, void* scratch, size_t scratch_bytes)
+{
+  if (!scratch) return fail(BPSF_EINVAL, "NULL scratch");
+  FixedScratch fx;
+  fx.base = scratch;
+  fx.bytes = scratch_bytes;
+  return decode_call(c, syndromes, priors, shots, p, corrections, converged, iterations, stream, &fx);
+}
+
+int bpsf::mix_scratch_stride(bpsf_mix m, const bpsf_params* p, int* out)
+{
+  if (!m || !p || !out) return fail(BPSF_EINVAL, "NULL argument");
+  int rc = check_params(p);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(m->mu);
+  // the same for every call size: the probes of mix_stride_max cover the
+  // mixed tile and both single-code tiles whatever the size
+  return mix_stride_max(m, SMALL_CALL_SHOTS, p, out);
+}
+
+size_t bpsf::mix_scratch_size(int n_codes, int64_t shots, int stride)
+{
+  return mix_fixed_bytes(n_codes, std::max<int64_t>(shots, 1), stride);
+}
+
+int bpsf::mix_scratch_bytes(bpsf_mix m, int64_t shots, const bpsf_params* p, size_t* out)
+{
+  if (!m || !p || !out) return fail(BPSF_EINVAL, "NULL argument");
+  int rc = check_params(p);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(m->mu);
+  int stride = 0;
+  if ((rc = mix_stride_max(m, std::max<int64_t>(shots, 1), p, &stride))) return rc;
+  *out = mix_fixed_bytes(m->n, std::max<int64_t>(shots, 1), stride);
+  return 0;
+}
+
+int bpsf::mix_decode_grouped_in(bpsf_mix m, const int64_t* counts, const uint8_t* syndromes, int64_t syn_stride,
+                                const double* const* priors, const bpsf_params* p, uint8_t* corrections,
+                                int64_t corr_stride, uint8_t* converged, int32_t* iterations, void* stream,
+                                void* scratch, size_t scratch_bytes)
+{
+  if (!m || !counts || !scratch) return fail(BPSF_EINVAL, "NULL argument");
+  int64_t shots = 0;
+  for (int i = 0; i < m->n; ++i) {
+    if (counts[i] < 0) return fail(BPSF_EINVAL, "counts[%d] < 0", i);
+    shots += counts[i];
+  }
+  FixedScratch fx;
+  fx.base = scratch;
+  fx.bytes = scratch_bytes;
+  return mix_decode(m, nullptr, counts, syndromes, syn_stride, priors, shots, p, corrections, corr_stride, converged,
+                    iterations, stream, &fx);
+}

@@ -2,7 +2,10 @@
 // Not part of the public ABI (that is include/bpsf.h).
 #pragma once
 
+#include <stddef.h>
 #include <stdint.h>
+
+#include "../../include/bpsf.h"
 
 namespace bpsf {
 
@@ -97,6 +100,24 @@ enum : int { FLAG_NO_EARLY_STOP = 1, FLAG_FORCE_PP = 2, FLAG_PRUNE = 4, FLAG_LAY
 
 // Sets the calling thread's message for bpsf_last_error and returns code.
 int report_error(int code, const char* msg);
+
+// For the request loop: the device bytes of the scratch of a grouped mixed
+// call of up to `shots` shots, and such a call with its scratch in a region
+// the caller owns (bpsf_mix_decode_grouped otherwise).
+int mix_scratch_bytes(bpsf_mix m, int64_t shots, const bpsf_params* p, size_t* out);
+// the same in two steps: the record words per shot that cover every call
+// size of the mix (computed once), then the bytes for a call of `shots`
+int mix_scratch_stride(bpsf_mix m, const bpsf_params* p, int* out);
+size_t mix_scratch_size(int n_codes, int64_t shots, int stride);
+// bpsf_decode with its scratch in a region the caller owns (a region sized by
+// mix_scratch_bytes for a mix holding the code is large enough)
+int decode_in(bpsf_code c, const uint8_t* syndromes, const double* priors, int64_t shots, const bpsf_params* p,
+              uint8_t* corrections, uint8_t* converged, int32_t* iterations, void* stream, void* scratch,
+              size_t scratch_bytes);
+int mix_decode_grouped_in(bpsf_mix m, const int64_t* counts, const uint8_t* syndromes, int64_t syn_stride,
+                          const double* const* priors, const bpsf_params* p, uint8_t* corrections,
+                          int64_t corr_stride, uint8_t* converged, int32_t* iterations, void* stream,
+                          void* scratch, size_t scratch_bytes);
 
 // One launch over several codes: every wave starts on a code chosen in
 // proportion to the codes' estimated work and moves on to the next code when

@@ -25,12 +25,12 @@ def _requests(n_req, seed, max_n=256):
     return hs, code, syns
 
 
-def _server(hs, batching=True, lanes=2, cap=4096):
+def _server(hs, batching=True, lanes=2, cap=4096, budget=0):
     from paper_2507_00254_amd import bpsf as B
     handles = [B.bpsf_load_code(h) for h in hs]
     prm = B.make_params(100, 20, 6, alpha=0.625, precision=B.PREC_FP32)
     srv = B.Server(handles, [np.full(h.shape[1], P) for h in hs], prm, lanes=lanes, max_batch_shots=cap,
-                   batching=batching)
+                   batching=batching, device_budget_bytes=budget)
     return B, handles, srv
 
 
@@ -120,3 +120,42 @@ def test_server_rejects_bad_requests():
         _close(B, handles, srv)
     with pytest.raises(B.BpsfError):
         _server(hs, batching=False, lanes=2)                         # per-request mode runs one lane
+
+
+@pytest.mark.parametrize("batching", [True, False])
+def test_small_memory_budget_queues_requests(batching):
+    """A device budget that holds one request of this size at a time: a burst
+    of such requests on two lanes queues for memory (the second lane waits
+    until the first batch returns its region), every result still equals the
+    shots decoded alone, the pool never holds more than its budget, and a
+    request larger than the pool can ever hold is refused at submit."""
+    budget = 768 * 1024
+    hs = [codes.get_code(nm).hx for nm in NAMES]
+    B, handles, srv = _server(hs, batching=batching, lanes=2 if batching else 1, cap=4096, budget=budget)
+    try:
+        mem = srv.memory()
+        print(f"pool {mem}", flush=True)
+        assert mem["budget"] == budget and 16 <= mem["max_request"] < 4096
+        n = max(1, (mem["max_request"] * 3) // 5)     # two of these never fit the pool together
+        rng = np.random.default_rng(9)
+        code = rng.integers(0, len(hs), 16)
+        syns = [shots.make_shots(hs[c], P, n, shots.stream_key(shots.MASTER_SEED, 951, i))[1]
+                for i, c in enumerate(code)]
+        alone = _alone(hs, code, syns)
+        reqs = [srv.submit(int(c), s) for c, s in zip(code, syns)]
+        for i, (rid, corr, conv, it) in enumerate(reqs):
+            srv.wait(rid)
+            assert np.array_equal(corr, alone[i][0]) and np.array_equal(conv, alone[i][1]), i
+            assert np.array_equal(it, alone[i][2]), i
+        mem = srv.memory()
+        cnt = srv.counters()
+        print(f"after: {mem} {cnt}", flush=True)
+        assert cnt["requests_done"] == len(reqs) and cnt["batches"] == len(reqs)   # one request per batch
+        assert 0 < mem["peak"] <= budget and mem["in_use"] == 0
+        if batching:
+            assert mem["waited_for_memory"] > 0
+        with pytest.raises(B.BpsfError) as ei:
+            srv.submit(0, np.zeros((mem["max_request"] + 1, hs[0].shape[0]), np.uint8))
+        assert ei.value.code == B.BPSF_EINVAL
+    finally:
+        _close(B, handles, srv)
