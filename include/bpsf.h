@@ -398,6 +398,34 @@ int bpsf_set_trial_table64(bpsf_code code, const uint64_t* masks, int64_t n_tria
 int bpsf_code_info(bpsf_code code, int32_t* M, int32_t* N, int32_t* edges, int32_t* row_weight,
                    int32_t* col_weight);
 
+/*
+ * The LDS layout that bpsf_load_code gives a code of the sparse family (the
+ * large irregular matrices, such as circuit-level detector error models),
+ * computed on the host alone, with no device call: for diagnostics and tests.
+ * Layout, not arithmetic: the message update of Section II-B is the same for
+ * any layout. Every argument is host memory the caller owns.
+ *
+ * row_ptr, col_idx, M, N: the matrix as in bpsf_load_code, checked the same
+ * way (same errors). info[BPSF_SPARSE_INFO_WORDS] receives: [0] the sparse
+ * family index, or -1 when the code takes another kernel family (then
+ * nothing else is written and the call returns 0); [1] message cells; [2]
+ * WMAX, row positions per check; [3] T, threads per workgroup; [4] CPT,
+ * checks per thread (internal check i belongs to thread i mod T); [5] DVMAX;
+ * [6] cells left above their bank's share in some half-wave group after the
+ * column placement; [7] row positions added over all groups; [8] cells moved
+ * to a position whose bank another lane of the group reads.
+ * Arrays, each may be NULL: roff [M * WMAX] the cell each internal check
+ * reads at each position; rw [M] the positions its half-wave reads (at least
+ * its weight); bits [N] first cell | weight << 16 of each internal bit; cperm
+ * [N] the caller's bit of each internal bit; rperm [M] the caller's check of
+ * each internal check. Cells from info[1] on are padding: DVMAX cells read
+ * past the last column, then T * CPT pad cells, +inf when a row reads them
+ * (thread t's pad for its check slot i is cell info[1] + DVMAX + t CPT + i).
+ */
+#define BPSF_SPARSE_INFO_WORDS 9
+int bpsf_sparse_layout(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, int32_t N, int32_t* info,
+                       uint16_t* roff, uint8_t* rw, uint32_t* bits, uint16_t* cperm, uint16_t* rperm);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* bpsf_last_error(void);
 

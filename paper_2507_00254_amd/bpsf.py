@@ -77,6 +77,7 @@ def _load():
     lib.bpsf_set_timing.argtypes = [vp, C.c_int]
     lib.bpsf_last_timing.argtypes = [vp, P(C.c_float)]
     lib.bpsf_code_info.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(i32)]
+    lib.bpsf_sparse_layout.argtypes = [P(i32), P(i32), i32, i32, P(i32), vp, vp, vp, vp, vp]
     lib.bpsf_tile_options.argtypes = [vp, P(i32), i32]
     lib.bpsf_reserve.argtypes = [vp, i64, P(bpsf_params)]
     lib.bpsf_set_trial_table.argtypes = [vp, vp, i64, i64]
@@ -503,6 +504,33 @@ def bpsf_code_info(handle) -> dict:
     vals = [C.c_int32() for _ in range(5)]
     _check(LIB.bpsf_code_info(C.c_void_p(handle), *[C.byref(v) for v in vals]))
     return dict(zip(("M", "N", "edges", "row_weight", "col_weight"), (v.value for v in vals)))
+
+
+SPARSE_INFO_WORDS = 9
+
+
+def bpsf_sparse_layout(h):
+    """The sparse family's LDS layout of a matrix (host only, no device):
+    None when the matrix takes another kernel family, else a dict with the
+    family, cells, WMAX, T, CPT, DVMAX, the layout's quality counts and the tables
+    roff [M, WMAX], rw [M], bits [N], cperm [N], rperm [M]."""
+    row_ptr, col_idx, m, n = _csr(h)
+    info = np.zeros(SPARSE_INFO_WORDS, np.int32)
+    ip = info.ctypes.data_as(C.POINTER(C.c_int32))
+    rp, ci = row_ptr.ctypes.data_as(C.POINTER(C.c_int32)), col_idx.ctypes.data_as(C.POINTER(C.c_int32))
+    _check(LIB.bpsf_sparse_layout(rp, ci, m, n, ip, None, None, None, None, None))
+    if info[0] < 0:
+        return None
+    wmax = int(info[2])
+    roff = np.zeros((m, wmax), np.uint16)
+    rw = np.zeros(m, np.uint8)
+    bits = np.zeros(n, np.uint32)
+    cperm = np.zeros(n, np.uint16)
+    rperm = np.zeros(m, np.uint16)
+    _check(LIB.bpsf_sparse_layout(rp, ci, m, n, ip, *(C.c_void_p(a.ctypes.data) for a in (roff, rw, bits, cperm, rperm))))
+    return {"family": int(info[0]), "cells": int(info[1]), "WMAX": wmax, "T": int(info[3]), "CPT": int(info[4]),
+            "DVMAX": int(info[5]), "overflow": int(info[6]), "extra_positions": int(info[7]), "folded": int(info[8]),
+            "roff": roff, "rw": rw, "bits": bits, "cperm": cperm, "rperm": rperm}
 
 
 def bpsf_bp_trace(handle, syndrome, priors, params: bpsf_params):

@@ -24,7 +24,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract
           "-Wno-unused-but-set-variable"]
 # units of libbpsf.so (lds_probe.hip builds liblds_probe.so on its own)
 UNITS = [("bpsf_kernels.hip", ["-fno-honor-nans"]), ("bpsf_wide.hip", ["-fno-honor-nans"]),
-         ("bpsf_sparse.hip", ["-fno-honor-nans"]), ("bpsf_api.hip", []), ("bpsf_server.hip", [])]
+         ("bpsf_sparse.hip", ["-fno-honor-nans"]), ("bpsf_sparse_layout.hip", []), ("bpsf_api.hip", []),
+         ("bpsf_server.hip", [])]
 
 
 def sources():

@@ -20,6 +20,7 @@
 #include "bpsf_internal.h"
 #include "bpsf_tiles.h"
 #include "bpsf_sparse.h"
+#include "bpsf_sparse_layout.h"
 
 using namespace bpsf;
 
@@ -567,32 +568,26 @@ namespace {
 // Mix words after the per-code counter blocks.
 enum : int { MIX_TASKS = 0, MIX_REC_ALLOC = MIX_MAX_CODES, MIX_BAD = MIX_MAX_CODES + 1, MIX_WORDS = MIX_MAX_CODES + 2 };
 
-}  // namespace
-
-extern "C" {
-
-const char* bpsf_last_error(void) { return g_err.c_str(); }
-
-int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, int32_t N, bpsf_code* out)
+// Checks a caller's CSR matrix and picks its kernel family, on the host
+// alone: fills M, N, E, rw_max, cw_max, W, DV, wide and sparse of *c.
+int classify_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, int32_t N, bpsf_code_s* c)
 {
-  if (!out) return fail(BPSF_EINVAL, "out is NULL");
-  *out = nullptr;
   if (!row_ptr || M < 1 || N < 1) return fail(BPSF_EINVAL, "need M >= 1, N >= 1 and row_ptr");
   if (row_ptr[0] != 0) return fail(BPSF_EINVAL, "row_ptr[0] must be 0");
-  for (int c = 0; c < M; ++c)
-    if (row_ptr[c + 1] < row_ptr[c]) return fail(BPSF_EINVAL, "row_ptr must be non-decreasing");
+  for (int r = 0; r < M; ++r)
+    if (row_ptr[r + 1] < row_ptr[r]) return fail(BPSF_EINVAL, "row_ptr must be non-decreasing");
   const int E = row_ptr[M];
   if (E > 0 && !col_idx) return fail(BPSF_EINVAL, "col_idx is NULL");
   std::vector<int> colw((size_t)N, 0);
   int rmin = 1 << 30, rmax = 0;
-  for (int c = 0; c < M; ++c) {
-    const int w = row_ptr[c + 1] - row_ptr[c];
+  for (int r = 0; r < M; ++r) {
+    const int w = row_ptr[r + 1] - row_ptr[r];
     rmin = std::min(rmin, w);
     rmax = std::max(rmax, w);
-    for (int e = row_ptr[c]; e < row_ptr[c + 1]; ++e) {
+    for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
       const int v = col_idx[e];
       if (v < 0 || v >= N) return fail(BPSF_EINVAL, "col_idx[%d] = %d out of range", e, v);
-      if (e > row_ptr[c] && v <= col_idx[e - 1]) return fail(BPSF_EINVAL, "row %d: columns must ascend", c);
+      if (e > row_ptr[r] && v <= col_idx[e - 1]) return fail(BPSF_EINVAL, "row %d: columns must ascend", r);
       ++colw[v];
     }
   }
@@ -605,8 +600,6 @@ int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, in
   if (rmin < 2) return fail(BPSF_ENOTSUP, "every check needs at least two bits");
   if (rmax > 255) return fail(BPSF_ENOTSUP, "rows heavier than 255");
 
-  bpsf_code_s* c = new (std::nothrow) bpsf_code_s;
-  if (!c) return fail(BPSF_ENOMEM, "handle");
   c->M = M;
   c->N = N;
   c->E = E;
@@ -640,12 +633,33 @@ int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, in
         c->DV = d.DVMAX;
       }
     }
-    if (c->wide < 0 && c->sparse < 0) {
-      delete c;
+    if (c->wide < 0 && c->sparse < 0)
       return fail(BPSF_ENOTSUP, "no kernel family for M=%d N=%d row weights %d..%d column weights %d..%d", M, N, rmin,
                   rmax, cmin, cmax);
-    }
   }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bpsf_last_error(void) { return g_err.c_str(); }
+
+int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, int32_t N, bpsf_code* out)
+{
+  if (!out) return fail(BPSF_EINVAL, "out is NULL");
+  *out = nullptr;
+  bpsf_code_s* c = new (std::nothrow) bpsf_code_s;
+  if (!c) return fail(BPSF_ENOMEM, "handle");
+  if (const int rc0 = classify_code(row_ptr, col_idx, M, N, c)) {
+    delete c;
+    return rc0;
+  }
+  const int E = c->E;
+  // the sparse family's LDS layout, computed before any device work
+  SparseTables sp;
+  if (c->sparse >= 0) sparse_tables(row_ptr, col_idx, M, N, sparse_desc(c->sparse), &sp);
   const int W = c->W, DV = c->DV;
 
   // checks of every bit in ascending order (0xffff past its weight), the
@@ -710,99 +724,19 @@ int bpsf_load_code(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, in
               hipMemcpy(c->row_w.p, roww.data(), roww.size(), hipMemcpyHostToDevice) != hipSuccess))
     rc = fail(BPSF_EDEVICE, "uploading code tables");
   if (!rc && c->sparse >= 0) {
-    // checks and bits renumbered by weight (ties by index), so that the rows
-    // and columns a wave handles together have nearly equal weights; edges
-    // in column-major order of the new bit numbers, a column's edges by
-    // ascending (caller's) check, which is the order of the sums; row
-    // offsets per new check, past the weight the pad cell of the thread
-    // slot that owns the check (new check ri belongs to thread ri mod T,
-    // slot ri / T; pad cells follow the message cells and DVMAX cells read
-    // past the last column)
-    const SparseDesc d = sparse_desc(c->sparse);
-    const int T = 64 * d.NW;
-    std::vector<int> rperm((size_t)M), cperm((size_t)N), rinv((size_t)M), cinv((size_t)N);
-    for (int i = 0; i < M; ++i) rperm[i] = i;
-    for (int i = 0; i < N; ++i) cperm[i] = i;
-    std::stable_sort(rperm.begin(), rperm.end(),
-                     [&](int x, int y) { return row_ptr[x + 1] - row_ptr[x] < row_ptr[y + 1] - row_ptr[y]; });
-    std::stable_sort(cperm.begin(), cperm.end(), [&](int x, int y) { return colw[x] < colw[y]; });
-    for (int i = 0; i < M; ++i) rinv[rperm[i]] = i;
-    for (int i = 0; i < N; ++i) cinv[cperm[i]] = i;
-    // A column of even weight takes one cell more: consecutive columns of a
-    // wave (equal weights) then start an odd number of cells apart, and the
-    // 32 lanes of a half-wave reading position j of their columns hit 32
-    // distinct LDS banks. Without room for the padding, none.
-    auto col_cells = [&](int w, bool pad) { return (uint32_t)(pad && (w % 2 == 0) ? w + 1 : w); };
-    uint32_t padded = 0;
-    for (int v = 0; v < N; ++v) padded += col_cells(colw[v], true);
-    const bool pad_cols = (int64_t)padded + d.DVMAX + (int64_t)T * d.CPT <= 65535;
-    std::vector<uint32_t> colptr((size_t)N + 1, 0);
-    for (int v = 0; v < N; ++v) colptr[v + 1] = colptr[v] + col_cells(colw[cperm[v]], pad_cols);
-    const int cells = (int)colptr[N];
-    c->sp_cells = cells;
-    auto pad_cell = [&](int ri) { return (uint32_t)(cells + d.DVMAX + (ri % T) * d.CPT + ri / T); };
-    std::vector<uint16_t> roff((size_t)M * d.WMAX);
-    for (int ri = 0; ri < M; ++ri)
-      for (int j = 0; j < d.WMAX; ++j) roff[(size_t)ri * d.WMAX + j] = (uint16_t)pad_cell(ri);
-    std::vector<uint8_t> srw((size_t)M);
-    std::vector<uint16_t> echk((size_t)(cells > 0 ? cells : 1), 0), rp16((size_t)M), cp16((size_t)N), ci16((size_t)N);
-    std::vector<uint32_t> bits((size_t)N);
-    std::vector<uint32_t> put(colptr.begin(), colptr.end() - 1);
-    std::vector<std::vector<uint32_t>> rcells((size_t)M);
-    for (int r = 0; r < M; ++r) {   // caller's checks in ascending order
-      const int ri = rinv[r];
-      srw[ri] = (uint8_t)(row_ptr[r + 1] - row_ptr[r]);
-      for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
-        const uint32_t cell = put[cinv[col_idx[e]]]++;
-        rcells[(size_t)ri].push_back(cell);
-        echk[cell] = (uint16_t)ri;
-      }
-    }
-    // The order of a row's positions is free (its minima and parity do not
-    // depend on it). For the 32 rows a half-wave reads together, position j
-    // of every row is chosen greedily among the row's unread cells so that
-    // the half-wave's reads at j fall in distinct LDS banks (cell mod 32)
-    // where it can; rows past their weight read their pad cells, whose banks
-    // are taken first.
-    for (int base = 0; base < M; base += 32) {
-      const int n = std::min(32, M - base);
-      int wmax = 0;
-      for (int l = 0; l < n; ++l) wmax = std::max(wmax, (int)rcells[(size_t)(base + l)].size());
-      std::vector<std::vector<uint32_t>> left(rcells.begin() + base, rcells.begin() + base + n);
-      for (int j = 0; j < wmax; ++j) {
-        uint32_t used = 0;
-        for (int l = 0; l < n; ++l)
-          if (left[(size_t)l].empty()) used |= 1u << (pad_cell(base + l) & 31u);
-        for (int l = 0; l < n; ++l) {
-          std::vector<uint32_t>& cand = left[(size_t)l];
-          if (cand.empty()) continue;
-          size_t pick = 0;
-          for (size_t q = 0; q < cand.size(); ++q)
-            if (!((used >> (cand[q] & 31u)) & 1u)) { pick = q; break; }
-          const uint32_t cell = cand[pick];
-          cand.erase(cand.begin() + (long)pick);
-          used |= 1u << (cell & 31u);
-          roff[(size_t)(base + l) * d.WMAX + j] = (uint16_t)cell;
-        }
-      }
-    }
-    for (int v = 0; v < N; ++v) {
-      bits[v] = colptr[v] | ((uint32_t)colw[cperm[v]] << 16);
-      cp16[v] = (uint16_t)cperm[v];
-      ci16[v] = (uint16_t)cinv[v];
-    }
-    for (int i = 0; i < M; ++i) rp16[i] = (uint16_t)rperm[i];
-    if (c->sp_roff.ensure(roff.size() * 2) || c->sp_echk.ensure(echk.size() * 2) || c->sp_bits.ensure(bits.size() * 4) ||
-        c->sp_rw.ensure(srw.size()) || c->sp_rperm.ensure(rp16.size() * 2) || c->sp_cperm.ensure(cp16.size() * 2) ||
-        c->sp_cinv.ensure(ci16.size() * 2))
+    const SparseTables& t = sp;
+    c->sp_cells = t.cells;
+    if (c->sp_roff.ensure(t.roff.size() * 2) || c->sp_echk.ensure(t.echk.size() * 2) ||
+        c->sp_bits.ensure(t.bits.size() * 4) || c->sp_rw.ensure(t.rw.size()) || c->sp_rperm.ensure(t.rperm.size() * 2) ||
+        c->sp_cperm.ensure(t.cperm.size() * 2) || c->sp_cinv.ensure(t.cinv.size() * 2))
       rc = fail(BPSF_ENOMEM, "sparse tables");
-    else if (hipMemcpy(c->sp_roff.p, roff.data(), roff.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
-             hipMemcpy(c->sp_echk.p, echk.data(), echk.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
-             hipMemcpy(c->sp_bits.p, bits.data(), bits.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-             hipMemcpy(c->sp_rw.p, srw.data(), srw.size(), hipMemcpyHostToDevice) != hipSuccess ||
-             hipMemcpy(c->sp_rperm.p, rp16.data(), rp16.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
-             hipMemcpy(c->sp_cperm.p, cp16.data(), cp16.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
-             hipMemcpy(c->sp_cinv.p, ci16.data(), ci16.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
+    else if (hipMemcpy(c->sp_roff.p, t.roff.data(), t.roff.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(c->sp_echk.p, t.echk.data(), t.echk.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(c->sp_bits.p, t.bits.data(), t.bits.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(c->sp_rw.p, t.rw.data(), t.rw.size(), hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(c->sp_rperm.p, t.rperm.data(), t.rperm.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(c->sp_cperm.p, t.cperm.data(), t.cperm.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(c->sp_cinv.p, t.cinv.data(), t.cinv.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
       rc = fail(BPSF_EDEVICE, "uploading sparse tables");
   }
   if (!rc && c->wide < 0 && c->sparse < 0) {
@@ -845,6 +779,34 @@ int bpsf_code_info(bpsf_code c, int32_t* M, int32_t* N, int32_t* edges, int32_t*
   if (edges) *edges = c->E;
   if (rw) *rw = c->rw_max;
   if (cw) *cw = c->cw_max;
+  return 0;
+}
+
+int bpsf_sparse_layout(const int32_t* row_ptr, const int32_t* col_idx, int32_t M, int32_t N, int32_t* info,
+                       uint16_t* roff, uint8_t* rw, uint32_t* bits, uint16_t* cperm, uint16_t* rperm)
+{
+  if (!info) return fail(BPSF_EINVAL, "info is NULL");
+  bpsf_code_s c;
+  if (const int rc = classify_code(row_ptr, col_idx, M, N, &c)) return rc;
+  for (int i = 0; i < BPSF_SPARSE_INFO_WORDS; ++i) info[i] = 0;
+  info[0] = c.sparse;
+  if (c.sparse < 0) return 0;
+  const SparseDesc d = sparse_desc(c.sparse);
+  SparseTables t;
+  sparse_tables(row_ptr, col_idx, M, N, d, &t);
+  info[1] = t.cells;
+  info[2] = d.WMAX;
+  info[3] = 64 * d.NW;
+  info[4] = d.CPT;
+  info[5] = d.DVMAX;
+  info[6] = t.overflow;
+  info[7] = t.extra_positions;
+  info[8] = t.folded;
+  if (roff) std::copy(t.roff.begin(), t.roff.end(), roff);
+  if (rw) std::copy(t.rw.begin(), t.rw.end(), rw);
+  if (bits) std::copy(t.bits.begin(), t.bits.end(), bits);
+  if (cperm) std::copy(t.cperm.begin(), t.cperm.end(), cperm);
+  if (rperm) std::copy(t.rperm.begin(), t.rperm.end(), rperm);
   return 0;
 }
 

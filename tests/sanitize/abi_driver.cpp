@@ -108,6 +108,66 @@ int main()
     c = nullptr;
   }
 
+  // an irregular matrix of the sparse family (columns of weight 2..6): its
+  // LDS layout on the host, then a load (which computes the layout before its
+  // first device call)
+  {
+    const int m = 900, n = 6000;
+    std::vector<std::vector<int32_t>> rows(m);
+    uint64_t x = 12345;
+    auto next = [&]() { x = x * 6364136223846793005ull + 1442695040888963407ull; return (uint32_t)(x >> 33); };
+    for (int v = 0; v < n; ++v) {
+      const int w = 2 + (int)(next() % 5);
+      std::vector<int> picked;
+      while ((int)picked.size() < w) {
+        const int r = (int)(next() % m);
+        bool dup = false;
+        for (int q : picked) dup = dup || q == r;
+        if (!dup) picked.push_back(r);
+      }
+      for (int r : picked) rows[(size_t)r].push_back(v);
+    }
+    std::vector<int32_t> rp(1, 0), ci;
+    int mm = 0;
+    for (int r = 0; r < m; ++r) {
+      if (rows[(size_t)r].size() < 2) continue;
+      ci.insert(ci.end(), rows[(size_t)r].begin(), rows[(size_t)r].end());
+      rp.push_back((int32_t)ci.size());
+      ++mm;
+    }
+    int32_t info[BPSF_SPARSE_INFO_WORDS];
+    EXPECT(bpsf_sparse_layout(rp.data(), ci.data(), mm, n, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr) ==
+           BPSF_EINVAL);
+    EXPECT(bpsf_sparse_layout(rp.data(), ci.data(), mm, n, info, nullptr, nullptr, nullptr, nullptr, nullptr) == 0);
+    EXPECT(info[0] >= 0);
+    if (info[0] >= 0) {
+      const int cells = info[1], wmax = info[2];
+      std::vector<uint16_t> roff((size_t)mm * wmax), cperm(n), rperm(mm);
+      std::vector<uint8_t> rw(mm);
+      std::vector<uint32_t> bits(n);
+      EXPECT(bpsf_sparse_layout(rp.data(), ci.data(), mm, n, info, roff.data(), rw.data(), bits.data(), cperm.data(),
+                                rperm.data()) == 0);
+      // every cell is read by exactly one check, once
+      std::vector<int> reads((size_t)cells, 0);
+      for (int r = 0; r < mm; ++r)
+        for (int j = 0; j < rw[(size_t)r]; ++j)
+          if (roff[(size_t)r * wmax + j] < cells) ++reads[roff[(size_t)r * wmax + j]];
+      int edges = 0, bad = 0;
+      for (int cell = 0; cell < cells; ++cell) {
+        edges += reads[(size_t)cell];
+        bad += reads[(size_t)cell] > 1;
+      }
+      EXPECT(edges == (int)ci.size() && bad == 0);
+    }
+    const int rc = bpsf_load_code(rp.data(), ci.data(), mm, n, &c);
+    EXPECT(rc == BPSF_OK || rc == BPSF_EDEVICE);
+    if (rc == BPSF_OK) bpsf_free_code(c);
+    c = nullptr;
+    // a code of another family has no sparse layout
+    EXPECT(bpsf_sparse_layout(rp_ok, ci_ok, 2, 3, info, nullptr, nullptr, nullptr, nullptr, nullptr) == 0 &&
+           info[0] == -1);
+  }
+
   // every entry point with a NULL handle or argument
   bpsf_params q = params();
   bpsf_stats st;

@@ -70,13 +70,13 @@ def hip_tools():
 
 
 def test_runtime_under_sanitizers(hip_tools):
-    """The host runtime (code loading, parameter and argument checks, server
-    set-up) built with host-side sanitizers, linked with the library's kernel
+    """The host runtime (code loading, the sparse family's layout, parameter
+    and argument checks, server set-up) built with host-side sanitizers, linked with the library's kernel
     objects and driven without a device: every entry point's rejection path,
     and a load that stops at the first device call when no GPU is present."""
     with tempfile.TemporaryDirectory() as d:
         objs, procs = [], []
-        for unit in ("bpsf_api", "bpsf_server"):
+        for unit in ("bpsf_api", "bpsf_server", "bpsf_sparse_layout"):
             obj = os.path.join(d, unit + ".o")
             procs.append(subprocess.Popen(
                 ["hipcc", "-std=c++17", "-O1", "-g", "--offload-arch=gfx950", "-Xclang", "-target-feature",
