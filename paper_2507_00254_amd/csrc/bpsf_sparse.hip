@@ -114,7 +114,7 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
   using F = SparseFamily<NW, CPT, WMAX, BPT, DVMAX>;
   constexpr int T = F::T, PL = F::PL, KMAX = F::KMAX;
   constexpr int CH = 8;   // row positions loaded together
-  static_assert(WMAX % CH == 0, "rows are read in chunks of CH positions");
+  static_assert(WMAX % CH == 0 && CH == 8, "rows are read in chunks of 8 positions (tails of 4, 2, 1)");
   const int M = a.M, N = a.N, E = a.E;
   const SparseLayout lay = sparse_layout(E, M, NW, DVMAX, CPT);
   extern __shared__ __align__(16) unsigned char smem[];
@@ -327,73 +327,64 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
         if (c < M) unsat |= (ub[c >> 5] >> (c & 31)) ^ (synbits >> i);
         msg[pad0 + i] = INFINITY;   // what my padded positions read
         const uint32_t rb = (uint32_t)__builtin_amdgcn_readfirstlane((int)rbound[i]);
-        // two passes over the row in chunks of CH positions (a chunk's loads
-        // are issued together): minima and sign parity, then the outputs; the
-        // row is read twice rather than held in registers
-        float m1 = INFINITY, m2 = INFINITY;
-        uint32_t P = synbits << (31 - i);                  // (-1)^{s_c}
+        // two passes over the row in chunks of CH positions whose loads are
+        // issued together: minima and sign parity, then the outputs; the row
+        // is read twice rather than held in registers. The wave's bound need
+        // not be a multiple of CH: its tail runs as chunks of 4, 2 and 1
+        // positions (at most three waits for loads, not one per position).
+        auto over_row = [&](auto&& chunk) {
 #pragma unroll
-        for (int jc = 0; jc < WMAX; jc += CH) {
-          if ((uint32_t)jc + CH <= rb) {
-            float x[CH];
-#pragma unroll
-            for (int q = 0; q < CH; ++q) {
-              const int j = jc + q;
-              x[q] = cell_ref(smem, roff[i][j >> 1], j & 1);
-            }
-#pragma unroll
-            for (int q = 0; q < CH; ++q) {
-              m2 = R::med3(m1, m2, R::absr(x[q]));
-              m1 = R::minr(m1, R::absr(x[q]));
-            }
-#pragma unroll
-            for (int q = 0; q < CH; q += 2) P = xor3(P, R::sw(x[q]), R::sw(x[q + 1]));   // two signs per op
-          } else if ((uint32_t)jc < rb) {
-            // the last, partial chunk: positions up to the wave's bound only
-#pragma unroll
-            for (int q = 0; q < CH; ++q) {
-              const int j = jc + q;
-              if ((uint32_t)j < rb) {
-                const float x = cell_ref(smem, roff[i][j >> 1], j & 1);
-                m2 = R::med3(m1, m2, R::absr(x));
-                m1 = R::minr(m1, R::absr(x));
-                P ^= R::sw(x);
+          for (int jc = 0; jc < WMAX; jc += CH) {
+            if ((uint32_t)jc + CH <= rb) {
+              chunk(jc, CH);
+            } else if ((uint32_t)jc < rb) {
+              const uint32_t rem = rb - (uint32_t)jc;   // 1 .. CH - 1, the same in every lane
+              if (rem & 4u) {
+                chunk(jc, 4);
+                if (rem & 2u) {
+                  chunk(jc + 4, 2);
+                  if (rem & 1u) chunk(jc + 6, 1);
+                } else if (rem & 1u) {
+                  chunk(jc + 4, 1);
+                }
+              } else if (rem & 2u) {
+                chunk(jc, 2);
+                if (rem & 1u) chunk(jc + 2, 1);
+              } else {
+                chunk(jc, 1);
               }
             }
           }
-        }
+        };
+        float m1 = INFINITY, m2 = INFINITY;
+        uint32_t P = synbits << (31 - i);                  // (-1)^{s_c}
+        over_row([&](const int j0, const int n) {          // positions j0 .. j0 + n - 1
+          float x[CH];
+#pragma unroll
+          for (int q = 0; q < n; ++q) x[q] = cell_ref(smem, roff[i][(j0 + q) >> 1], (j0 + q) & 1);
+#pragma unroll
+          for (int q = 0; q < n; ++q) {
+            m2 = R::med3(m1, m2, R::absr(x[q]));
+            m1 = R::minr(m1, R::absr(x[q]));
+          }
+#pragma unroll
+          for (int q = 0; q + 1 < n; q += 2) P = xor3(P, R::sw(x[q]), R::sw(x[q + 1]));   // two signs per op
+          if (n & 1) P ^= R::sw(x[n - 1]);
+        });
         float s1 = R::flip(alpha * m1, P), s2 = R::flip(alpha * m2, P);
         R::opaque(s1);
         R::opaque(s2);
         // (addresses recomputed for the second pass rather than kept)
 #pragma unroll
         for (int j = 0; j < WMAX / 2; ++j) asm volatile("" : "+v"(roff[i][j]));
+        over_row([&](const int j0, const int n) {
+          float x[CH];
 #pragma unroll
-        for (int jc = 0; jc < WMAX; jc += CH) {
-          if ((uint32_t)jc + CH <= rb) {
-            float x[CH];
+          for (int q = 0; q < n; ++q) x[q] = cell_ref(smem, roff[i][(j0 + q) >> 1], (j0 + q) & 1);
 #pragma unroll
-            for (int q = 0; q < CH; ++q) {
-              const int j = jc + q;
-              x[q] = cell_ref(smem, roff[i][j >> 1], j & 1);
-            }
-#pragma unroll
-            for (int q = 0; q < CH; ++q) {
-              const int j = jc + q;
-              cell_ref(smem, roff[i][j >> 1], j & 1) = R::flip(R::absr(x[q]) == m1 ? s2 : s1, R::sw(x[q]));
-            }
-          } else if ((uint32_t)jc < rb) {
-#pragma unroll
-            for (int q = 0; q < CH; ++q) {
-              const int j = jc + q;
-              if ((uint32_t)j < rb) {
-                __attribute__((address_space(3))) float& cx = cell_ref(smem, roff[i][j >> 1], j & 1);
-                const float x = cx;
-                cx = R::flip(R::absr(x) == m1 ? s2 : s1, R::sw(x));
-              }
-            }
-          }
-        }
+          for (int q = 0; q < n; ++q)
+            cell_ref(smem, roff[i][(j0 + q) >> 1], (j0 + q) & 1) = R::flip(R::absr(x[q]) == m1 ? s2 : s1, R::sw(x[q]));
+        });
       }
       const unsigned long long anyw = __ballot((unsat & 1u) != 0u);
       if ((g & 63) == 0) flags[(iter & 1) * (NW + 1) + (g >> 6)] = anyw != 0ull ? 1u : 0u;
