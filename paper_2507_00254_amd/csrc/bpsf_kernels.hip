@@ -253,8 +253,17 @@ __device__ __forceinline__ void decode_code(const Args& a, bool own_first)
     } else {
       long long f, ti;
       if constexpr (MODE == MODE_CAND) {
-        f = t / a.n_trials;
-        ti = t - f * a.n_trials;
+        if (a.flags & FLAG_PRUNE) {
+          // trial-major: trial 0 of every failed shot, then trial 1, ...; a
+          // shot's later trials are then taken after its earlier ones have
+          // run, and skipped once one of them has succeeded
+          const long long F = n_tasks / a.n_trials;
+          ti = t / F;
+          f = t - ti * F;
+        } else {
+          f = t / a.n_trials;
+          ti = t - f * a.n_trials;
+        }
       } else {
         f = t;
       }

@@ -124,8 +124,14 @@ __device__ __forceinline__ void decode_wide(const Args& a)
       int skip = 0;
       if (MODE != MODE_MAIN && t0 < n_tasks) {
         if (MODE == MODE_CAND) {
-          f = t0 / a.n_trials;
-          ti = t0 - f * a.n_trials;
+          if (a.flags & FLAG_PRUNE) {   // trial-major (as in the one-wave kernels)
+            const long long F = n_tasks / a.n_trials;
+            ti = t0 / F;
+            f = t0 - ti * F;
+          } else {
+            f = t0 / a.n_trials;
+            ti = t0 - f * a.n_trials;
+          }
         } else {
           f = t0;
         }
