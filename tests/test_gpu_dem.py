@@ -82,6 +82,29 @@ def test_dem_pruning_and_edges():
     assert (z["correction"] == 0).all() and (z["converged"] == 1).all() and (z["iterations"] == 1).all()
 
 
+def test_dem_pruned_trials_run_near_the_sequential_minimum():
+    """First success with pruning: trials are taken in trial-major order, so
+    a shot's later trials start after its earlier ones and are skipped once
+    one has succeeded. With many failed shots the trial iterations come close
+    to the oracle's, which runs a shot's trials one after another and stops
+    at the first success (no parallel schedule can run fewer); results are
+    the oracle's on every shot."""
+    dem = _dem("bb144", 12, 0.003)
+    _, syn, _ = circuit.sample(dem, 3000, shots.stream_key(shots.MASTER_SEED, 1407))
+    prm = U.oracle_params(max_iter=100, cand_max_iter=100, k=16, select_mode=1, alpha=0.0, flags=4)
+    masks = trials.sample_trial_list(16, 6, 5, shots.stream_key(shots.MASTER_SEED, 1408))
+    from tests.test_gpu_trials import _decode_table as dt
+    from oracle import oracle as O
+    g = dt(dem.h, syn, dem.priors, prm, masks)
+    o = O.bpsf_batch(dem.h, syn, dem.priors, prm, prec="f32", threads=16, masks=masks)
+    assert len(U.mismatches(g, o)) == 0
+    seq = int(o["trial_iterations"].sum())
+    got = g["stats"]["trial_iterations"]
+    print(f"failed shots {g['stats']['failed_shots']}: trial iterations {got} (sequential {seq})", flush=True)
+    assert g["stats"]["failed_shots"] > 256     # more failed shots than workgroups in flight
+    assert seq <= got <= 1.25 * seq
+
+
 def test_dem_refuses_unsupported_requests():
     import torch
     from paper_2507_00254_amd import bpsf as B
