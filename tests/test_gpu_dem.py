@@ -105,6 +105,32 @@ def test_dem_pruned_trials_run_near_the_sequential_minimum():
     assert seq <= got <= 1.25 * seq
 
 
+def test_rows_of_the_largest_weight_decode_like_the_oracle():
+    """A matrix whose rows all have weight 48, the sparse family's largest:
+    its layout folds some cells into positions that share a bank; decoding
+    is still the oracle's on every shot (first BP and trials)."""
+    rng = np.random.default_rng(5)
+    m, n = 64, 768
+    cols = np.tile(np.arange(n), 5)[:48 * m]
+    rng.shuffle(cols)
+    h = np.zeros((m, n), np.uint8)
+    for r in range(m):
+        h[r, np.unique(cols[r * 48:(r + 1) * 48])] = 1
+        while h[r].sum() < 48:
+            h[r, rng.integers(n)] = 1
+    h = h[:, h.sum(0) > 0]
+    from paper_2507_00254_amd import bpsf as B
+    assert B.bpsf_sparse_layout(h)["folded"] > 0
+    p = 0.004
+    err, syn = shots.make_shots(h, p, 400, shots.stream_key(shots.MASTER_SEED, 1409))
+    for prm in (U.oracle_params(max_iter=50, cand_max_iter=20, k=6, alpha=0.0),
+                U.oracle_params(max_iter=50, cand_max_iter=20, k=6, alpha=0.625)):
+        g = U.gpu_decode(h, syn, p, prm)
+        o = U.oracle_decode(h, syn, p, prm, precision="f32")
+        assert len(U.mismatches(g, o)) == 0
+        print(f"failed first BPs {g['stats']['failed_shots']}", flush=True)
+
+
 def test_dem_refuses_unsupported_requests():
     import torch
     from paper_2507_00254_amd import bpsf as B

@@ -121,6 +121,26 @@ def test_layout_of_random_irregular_matrices(B):
         _check_tables(h, L)
 
 
+def test_layout_with_rows_of_the_largest_weight(B):
+    """Rows of weight WMAX leave no spare position: where a group's bank
+    loads exceed it, cells fold into positions that share a bank (a slower
+    read, never a wrong one); the tables stay exact."""
+    rng = np.random.default_rng(5)
+    m, n = 64, 768
+    cols = np.tile(np.arange(n), 5)[:48 * m]
+    rng.shuffle(cols)
+    h = np.zeros((m, n), np.uint8)
+    for r in range(m):
+        h[r, np.unique(cols[r * 48:(r + 1) * 48])] = 1
+        while h[r].sum() < 48:
+            h[r, rng.integers(n)] = 1
+    h = h[:, h.sum(0) > 0]
+    L = B.bpsf_sparse_layout(h)
+    assert L is not None and L["WMAX"] == 48
+    assert L["folded"] > 0
+    _check_tables(h, L)
+
+
 def test_layout_is_deterministic(B, dem144):
     a, b = B.bpsf_sparse_layout(dem144), B.bpsf_sparse_layout(dem144)
     for k in ("roff", "rw", "bits", "cperm", "rperm"):
