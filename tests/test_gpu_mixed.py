@@ -70,6 +70,33 @@ def test_mixed_five_codes_match_single_calls_and_oracle(precision, per):
         assert st["errors"] == 0
 
 
+def test_mixed_first_success_with_pruning():
+    """First success with pruning in one mixed call (trial tasks of every
+    code taken trial index first): every shot equals the oracle's, which
+    keeps the lowest successful trial; pruning runs fewer trial iterations
+    than the unpruned mixed call."""
+    p = 0.06
+    hs = [codes.get_code(n).hx for n in NAMES]
+    sc, syn, _, _ = shots.mixed_batch(hs, p, 600, shots.stream_key(shots.MASTER_SEED, 903))
+    pri = [np.full(h.shape[1], p) for h in hs]
+    full = _mix_decode(hs, sc, syn, pri, U.oracle_params(k=6, select_mode=1))
+    pruned = _mix_decode(hs, sc, syn, pri, U.oracle_params(k=6, select_mode=1, flags=4))
+    assert full["bad"] == 0 and pruned["bad"] == 0
+    saved = 0
+    for c, h in enumerate(hs):
+        g, sel = _per_code(pruned, sc, c, h.shape[1])
+        o = U.oracle_decode(h, syn[sel, :h.shape[0]], p, U.oracle_params(k=6, select_mode=1), precision="f32")
+        assert len(U.mismatches(g, o)) == 0, NAMES[c]
+        f, _ = _per_code(full, sc, c, h.shape[1])
+        assert len(U.mismatches(g, f)) == 0, NAMES[c]
+        sp, sf = pruned["stats"][c], full["stats"][c]
+        assert sp["failed_shots"] == sf["failed_shots"] > 0 and sp["errors"] == 0
+        assert sp["trial_iterations"] <= sf["trial_iterations"]
+        saved += sf["trial_iterations"] - sp["trial_iterations"]
+    print(f"trial iterations saved by pruning: {saved}", flush=True)
+    assert saved > 0
+
+
 def test_mixed_missing_code_and_bad_indices():
     p = 0.06
     hs = [codes.get_code(n).hx for n in ("bb72", "bb144", "bb288")]
