@@ -451,6 +451,11 @@ def run_dem(args):
         # events around the call), the first args.dem_latency_calls shots
         lat = []
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        if args.dem_latency_calls > 0:
+            # one untimed call: a call this small keeps its trials' corrections,
+            # and the first one sizes that buffer
+            B.bpsf_decode(handle, s[:1], dem.priors, prm if phi == 16 else prm50, corr[:1], conv[:1], it[:1], stream)
+            torch.cuda.synchronize()
         for i in range(min(args.dem_latency_calls, n)):
             ev0.record(stream)
             B.bpsf_decode(handle, s[i:i + 1], dem.priors, prm if phi == 16 else prm50, corr[i:i + 1], conv[i:i + 1],
@@ -692,6 +697,8 @@ def main():
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         sub = s[:256]
         o1, o2, o3 = corr[:256], conv[:256], it[:256]
+        B.bpsf_decode(handle, sub, pri, prm, o1, o2, o3, stream)   # untimed: the first call of this tile
+        torch.cuda.synchronize()
         for i in range(args.latency_calls):
             off = (i * 256) % (n - 256)
             sub = s[off:off + 256]

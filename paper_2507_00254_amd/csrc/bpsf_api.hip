@@ -91,6 +91,7 @@ struct bpsf_code_s {
   int sparse = -1;
   int sp_cells = 0;          // message cells (edges plus column padding)
   DevBuf sp_roff, sp_rw, sp_bits, sp_echk, sp_rperm, sp_cperm, sp_cinv;
+  DevBuf sp_trial_bits;      // kept corrections of converged trials (small calls)
   std::vector<int32_t> ell_host;
   // channel LLR cache
   std::vector<double> priors;
@@ -461,6 +462,9 @@ struct FixedScratch {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Largest buffer of kept trial corrections a sparse-family call allocates.
+constexpr size_t SPARSE_TRIAL_BITS_MAX = (size_t)32 << 20;
+
 int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl, const FixedScratch* fixed = nullptr)
 {
   const bool layered = (p->flags & BPSF_FLAG_LAYERED) != 0;
@@ -507,6 +511,16 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl, con
   const bool fp64 = p->precision == BPSF_PREC_FP64;
   if (c->sparse >= 0) {
     const SparseDesc d = sparse_desc(c->sparse);
+    // A call whose trials' corrections fit SPARSE_TRIAL_BITS_MAX keeps them
+    // (one word per thread per trial of every possible record), so the
+    // re-run phase copies the winner's instead of decoding up to
+    // cand_max_iter more iterations: most of a one-syndrome call's tail.
+    // Not with the fixed scratch of bpsf_decode_noalloc.
+    const size_t tb = sizeof(uint32_t) * (size_t)cap * (size_t)(a.n_trials > 0 ? a.n_trials : 1) * (size_t)(64 * d.NW);
+    if (!fixed && p->k > 0 && tb <= SPARSE_TRIAL_BITS_MAX) {
+      if (c->sp_trial_bits.ensure(tb)) return fail(BPSF_ENOMEM, "trial corrections for %lld shots", (long long)shots);
+      a.trial_bits = static_cast<uint32_t*>(c->sp_trial_bits.p);
+    }
     pl->lds = sparse_layout(c->sp_cells, c->M, d.NW, d.DVMAX, d.CPT).total;
     if (pl->lds > c->lds_max)
       return fail(BPSF_ENOTSUP, "the %d edges of this code need %zu bytes of LDS per workgroup, the device gives %zu",

@@ -239,6 +239,25 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
     const long long t = task[0];
     if (t >= n_tasks) break;
     if (task[3]) continue;
+    if constexpr (MODE == MODE_EMIT) {
+      if (a.trial_bits) {
+        // the winner's correction as the trial kernel kept it: no decode
+        const int f = (int)task[1], ti = (int)task[2];
+        const int32_t* rr = a.records + (long long)f * rstride;
+        const long long sh = rr[REC_SHOT];
+        const uint32_t e = a.trial_bits[((long long)f * a.n_trials + ti) * T + g];
+        uint8_t* out = a.corrections + sh * a.corr_stride;
+#pragma unroll
+        for (int i = 0; i < BPT; ++i)
+          if ((vmask >> i) & 1u) out[caller_bit(a, g + T * i)] = (uint8_t)((e >> i) & 1u);
+        if (g == 0) {
+          const unsigned long long kk = a.keys[f];
+          a.converged[sh] = 1;
+          a.iterations[sh] = rr[REC_MAIN_ITERS] + (int)(kk & ((1ull << KEY_ITER_BITS) - 1ull));
+        }
+        continue;
+      }
+    }
 
     // ---- inputs: s into LDS bits (internal check order), u = 0 ----
     long long shot = 0;
@@ -531,6 +550,8 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
         }
       }
     } else if constexpr (MODE == MODE_CAND) {
+      if (a.trial_bits && conv)
+        a.trial_bits[((long long)rec * a.n_trials + trial) * T + g] = (hb ^ tbits) & vmask;
       const uint32_t w = wg_reduce<NW>((uint32_t)__popc((hb ^ tbits) & vmask), OpAdd(), red);
       if (g == 0) {
         st_iters += (unsigned long long)iter;
