@@ -462,8 +462,9 @@ struct FixedScratch {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Largest buffer of kept trial corrections a sparse-family call allocates.
-constexpr size_t SPARSE_TRIAL_BITS_MAX = (size_t)32 << 20;
+// Largest buffer of kept trial corrections of a sparse-family code (grown
+// once per handle and kept).
+constexpr size_t SPARSE_TRIAL_BITS_MAX = (size_t)256 << 20;
 
 int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl, const FixedScratch* fixed = nullptr)
 {
@@ -511,15 +512,19 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl, con
   const bool fp64 = p->precision == BPSF_PREC_FP64;
   if (c->sparse >= 0) {
     const SparseDesc d = sparse_desc(c->sparse);
-    // A call whose trials' corrections fit SPARSE_TRIAL_BITS_MAX keeps them
-    // (one word per thread per trial of every possible record), so the
-    // re-run phase copies the winner's instead of decoding up to
-    // cand_max_iter more iterations: most of a one-syndrome call's tail.
-    // Not with the fixed scratch of bpsf_decode_noalloc.
-    const size_t tb = sizeof(uint32_t) * (size_t)cap * (size_t)(a.n_trials > 0 ? a.n_trials : 1) * (size_t)(64 * d.NW);
-    if (!fixed && p->k > 0 && tb <= SPARSE_TRIAL_BITS_MAX) {
-      if (c->sp_trial_bits.ensure(tb)) return fail(BPSF_ENOMEM, "trial corrections for %lld shots", (long long)shots);
+    // The trials of the first records (as many as SPARSE_TRIAL_BITS_MAX
+    // holds, one word per thread per trial) keep their corrections, so the
+    // re-run phase copies those winners' instead of decoding up to
+    // cand_max_iter more iterations of one workgroup each: most of a
+    // one-syndrome call's tail, and the whole re-run phase of a call whose
+    // failed shots fit. Not with the fixed scratch of bpsf_decode_noalloc.
+    const size_t per_rec = sizeof(uint32_t) * (size_t)(a.n_trials > 0 ? a.n_trials : 1) * (size_t)(64 * d.NW);
+    const int64_t recs = std::min<int64_t>(cap, (int64_t)(SPARSE_TRIAL_BITS_MAX / per_rec));
+    if (!fixed && p->k > 0 && recs > 0) {
+      if (c->sp_trial_bits.ensure(per_rec * (size_t)recs))
+        return fail(BPSF_ENOMEM, "trial corrections of %lld records", (long long)recs);
       a.trial_bits = static_cast<uint32_t*>(c->sp_trial_bits.p);
+      a.trial_bits_recs = recs;
     }
     pl->lds = sparse_layout(c->sp_cells, c->M, d.NW, d.DVMAX, d.CPT).total;
     if (pl->lds > c->lds_max)

@@ -90,11 +90,12 @@ struct Args {
   int64_t rec_cap;
   unsigned long long* keys;  // [cap]
   unsigned long long* counters;  // [CNT_WORDS] of this code
-  // sparse family, calls small enough: [record][trial][T] words, thread g's
-  // bits of every converged trial's undone correction (its own bit slots);
-  // the re-run phase then copies the winner's instead of decoding it again
-  // (NULL: the re-run phase decodes it)
+  // sparse family: [record][trial][T] words, thread g's bits of every
+  // converged trial's undone correction (its own bit slots), for the first
+  // trial_bits_recs records; the re-run phase copies the winner's for those
+  // records instead of decoding it again (NULL: every winner is decoded)
   uint32_t* trial_bits;
+  int64_t trial_bits_recs;
   // per-iteration records of slot 0 (debug entry point only)
   void* trace_lout;          // [max_iter][N] Real
   void* trace_c2v;           // [max_iter][M*W] Real (row-major edge order)

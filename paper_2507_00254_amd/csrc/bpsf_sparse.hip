@@ -240,7 +240,7 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
     if (t >= n_tasks) break;
     if (task[3]) continue;
     if constexpr (MODE == MODE_EMIT) {
-      if (a.trial_bits) {
+      if (a.trial_bits && task[1] < a.trial_bits_recs) {
         // the winner's correction as the trial kernel kept it: no decode
         const int f = (int)task[1], ti = (int)task[2];
         const int32_t* rr = a.records + (long long)f * rstride;
@@ -550,7 +550,7 @@ __device__ __forceinline__ void decode_sparse(const Args& a)
         }
       }
     } else if constexpr (MODE == MODE_CAND) {
-      if (a.trial_bits && conv)
+      if (a.trial_bits && conv && rec < a.trial_bits_recs)
         a.trial_bits[((long long)rec * a.n_trials + trial) * T + g] = (hb ^ tbits) & vmask;
       const uint32_t w = wg_reduce<NW>((uint32_t)__popc((hb ^ tbits) & vmask), OpAdd(), red);
       if (g == 0) {

@@ -106,27 +106,32 @@ def test_dem_pruned_trials_run_near_the_sequential_minimum():
 
 
 def test_kept_trial_corrections_equal_the_rerun():
-    """A call small enough to keep every converged trial's correction copies
-    the winner's in its last phase; a larger call decodes the winner again.
-    The same shots give the same corrections, converged flags and iteration
-    counts either way, and the oracle's."""
+    """The trials of the first failed shots keep their corrections (256 MiB
+    of them: 655 records at 100 trials) and the last phase copies those
+    winners' corrections; later records decode their winner again. A call
+    with more failed shots than that mixes both; a small call copies every
+    winner. The same shots give the same corrections, converged flags and
+    iteration counts either way, and the oracle's."""
     dem = _dem("bb144", 12, 0.003)
-    _, syn, _ = circuit.sample(dem, 2000, shots.stream_key(shots.MASTER_SEED, 1410))
-    prm = U.oracle_params(max_iter=100, cand_max_iter=100, k=16, select_mode=0, alpha=0.0)
-    masks = trials.sample_trial_list(16, 6, 5, shots.stream_key(shots.MASTER_SEED, 1411))
-    big = _decode_table(dem.h, syn, dem.priors, prm, masks)          # 2000 shots: re-run
-    small = _decode_table(dem.h, syn[:150], dem.priors, prm, masks)  # 150 shots: kept corrections
-    assert big["stats"]["rerun_iterations"] > 0 and small["stats"]["rerun_iterations"] == 0
-    assert small["stats"]["failed_shots"] > 0 and small["stats"]["errors"] == 0
+    _, syn, _ = circuit.sample(dem, 10_000, shots.stream_key(shots.MASTER_SEED, 1410))
+    prm = U.oracle_params(max_iter=100, cand_max_iter=100, k=50, select_mode=0, alpha=0.0)
+    masks = trials.sample_trial_list(50, 10, 10, shots.stream_key(shots.MASTER_SEED, 1411))
+    kept = (256 << 20) // (len(masks) * 1024 * 4)
+    big = _decode_table64(dem.h, syn, dem.priors, prm, masks)
+    print(f"failed shots {big['stats']['failed_shots']}, kept records {kept}", flush=True)
+    assert big["stats"]["failed_shots"] > kept and big["stats"]["rerun_iterations"] > 0
+    small = _decode_table64(dem.h, syn[:150], dem.priors, prm, masks)
+    assert small["stats"]["rerun_iterations"] == 0
+    assert small["stats"]["failed_shots"] > 0 and small["stats"]["errors"] == 0 and big["stats"]["errors"] == 0
     assert len(U.mismatches(small, {k: v[:150] for k, v in big.items() if k != "stats"})) == 0
     from oracle import oracle as O
     o = O.bpsf_batch(dem.h, syn[:150], dem.priors, prm, prec="f32", threads=16, masks=masks)
     assert len(U.mismatches(small, o)) == 0
     # one syndrome per call, the latency path
-    for i in np.nonzero((o["winner"] >= 0))[0][:3]:
-        one = _decode_table(dem.h, syn[i:i + 1], dem.priors, prm, masks)
-        assert len(U.mismatches(one, {k: v[i:i + 1] for k, v in o.items() if k in ("correction", "converged",
-                                                                                  "iterations")})) == 0
+    for i in np.nonzero(o["winner"] >= 0)[0][:3]:
+        one = _decode_table64(dem.h, syn[i:i + 1], dem.priors, prm, masks)
+        assert len(U.mismatches(one, {k: v[i:i + 1] for k, v in o.items()
+                                      if k in ("correction", "converged", "iterations")})) == 0
 
 
 def test_rows_of_the_largest_weight_decode_like_the_oracle():
