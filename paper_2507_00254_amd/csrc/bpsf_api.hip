@@ -91,7 +91,7 @@ struct bpsf_code_s {
   int sparse = -1;
   int sp_cells = 0;          // message cells (edges plus column padding)
   DevBuf sp_roff, sp_rw, sp_bits, sp_echk, sp_rperm, sp_cperm, sp_cinv;
-  DevBuf sp_trial_bits;      // kept corrections of converged trials (small calls)
+
   std::vector<int32_t> ell_host;
   // channel LLR cache
   std::vector<double> priors;
@@ -107,6 +107,7 @@ struct bpsf_code_s {
   DevBuf masks;
   // scratch
   DevBuf records, keys, counters;
+  DevBuf trial_bits;          // kept corrections of converged trials (single-code calls)
   unsigned long long* last_counters = nullptr;   // counters of the last decode call (its scratch)
   int tuned_D = 0;            // decodes per wave (0: the most that fit)
   int tuned_wpc = 0;          // resident waves per CU of the persistent grids (0: as many as fit)
@@ -462,9 +463,28 @@ struct FixedScratch {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Largest buffer of kept trial corrections of a sparse-family code (grown
-// once per handle and kept).
-constexpr size_t SPARSE_TRIAL_BITS_MAX = (size_t)256 << 20;
+// Largest buffer of kept trial corrections of a code (grown once per handle
+// and kept).
+constexpr size_t TRIAL_BITS_MAX = (size_t)256 << 20;
+
+// The trials of a single-code call's first records (as many as
+// TRIAL_BITS_MAX holds, one word per lane of a decode per trial) keep their
+// corrections, so the re-run phase copies those winners' corrections instead
+// of decoding up to cand_max_iter more iterations each: most of a small
+// call's tail, and the whole re-run phase of a call whose failed shots fit.
+// Not with the fixed scratch of bpsf_decode_noalloc.
+int keep_trial_bits(bpsf_code_s* c, const bpsf_params* p, int lanes, int64_t cap, const FixedScratch* fixed, Args* a)
+{
+  if (fixed || p->k <= 0) return 0;
+  const size_t per_rec = sizeof(uint32_t) * (size_t)(a->n_trials > 0 ? a->n_trials : 1) * (size_t)lanes;
+  const int64_t recs = std::min<int64_t>(cap, (int64_t)(TRIAL_BITS_MAX / per_rec));
+  if (recs <= 0) return 0;
+  if (c->trial_bits.ensure(per_rec * (size_t)recs))
+    return fail(BPSF_ENOMEM, "trial corrections of %lld records", (long long)recs);
+  a->trial_bits = static_cast<uint32_t*>(c->trial_bits.p);
+  a->trial_bits_recs = recs;
+  return 0;
+}
 
 int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl, const FixedScratch* fixed = nullptr)
 {
@@ -512,20 +532,7 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl, con
   const bool fp64 = p->precision == BPSF_PREC_FP64;
   if (c->sparse >= 0) {
     const SparseDesc d = sparse_desc(c->sparse);
-    // The trials of the first records (as many as SPARSE_TRIAL_BITS_MAX
-    // holds, one word per thread per trial) keep their corrections, so the
-    // re-run phase copies those winners' instead of decoding up to
-    // cand_max_iter more iterations of one workgroup each: most of a
-    // one-syndrome call's tail, and the whole re-run phase of a call whose
-    // failed shots fit. Not with the fixed scratch of bpsf_decode_noalloc.
-    const size_t per_rec = sizeof(uint32_t) * (size_t)(a.n_trials > 0 ? a.n_trials : 1) * (size_t)(64 * d.NW);
-    const int64_t recs = std::min<int64_t>(cap, (int64_t)(SPARSE_TRIAL_BITS_MAX / per_rec));
-    if (!fixed && p->k > 0 && recs > 0) {
-      if (c->sp_trial_bits.ensure(per_rec * (size_t)recs))
-        return fail(BPSF_ENOMEM, "trial corrections of %lld records", (long long)recs);
-      a.trial_bits = static_cast<uint32_t*>(c->sp_trial_bits.p);
-      a.trial_bits_recs = recs;
-    }
+    if ((rc = keep_trial_bits(c, p, 64 * d.NW, cap, fixed, &a))) return rc;
     pl->lds = sparse_layout(c->sp_cells, c->M, d.NW, d.DVMAX, d.CPT).total;
     if (pl->lds > c->lds_max)
       return fail(BPSF_ENOTSUP, "the %d edges of this code need %zu bytes of LDS per workgroup, the device gives %zu",
@@ -552,6 +559,7 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl, con
     }
     return 0;
   }
+  if ((rc = keep_trial_bits(c, p, 64 / t.D, cap, fixed, &a))) return rc;
   pl->lds = tile_lds(c, t, fp64, c->uniform, layered);
   if (pl->lds > c->lds_max)
     return fail(BPSF_ENOTSUP, "this tile needs %zu bytes of LDS per workgroup, the device gives %zu", pl->lds,

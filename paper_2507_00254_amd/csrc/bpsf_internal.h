@@ -90,10 +90,11 @@ struct Args {
   int64_t rec_cap;
   unsigned long long* keys;  // [cap]
   unsigned long long* counters;  // [CNT_WORDS] of this code
-  // sparse family: [record][trial][T] words, thread g's bits of every
-  // converged trial's undone correction (its own bit slots), for the first
-  // trial_bits_recs records; the re-run phase copies the winner's for those
-  // records instead of decoding it again (NULL: every winner is decoded)
+  // single-code calls: [record][trial][lanes of a decode] words, each lane's
+  // bits of every converged trial's undone correction (its own bit items or
+  // slots), for the first trial_bits_recs records; the re-run phase copies
+  // the winner's for those records instead of decoding it again (NULL:
+  // every winner is decoded; mixed calls and the wide family)
   uint32_t* trial_bits;
   int64_t trial_bits_recs;
   // per-iteration records of slot 0 (debug entry point only)

@@ -48,7 +48,10 @@ namespace bpsf {
 // checks layer by layer, each reading and updating the bits' posteriors)
 // instead of flooding. own_first: the wave's first chunk of tasks follows
 // from its block index instead of the shared counter.
-template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE, bool TRACE, bool LAY>
+// KEEP: the launch may keep trial corrections (Args::trial_bits), which a
+// single-code launch does and a mixed launch never does (the code is then
+// left out of the mixed kernel, whose registers are tighter)
+template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE, bool TRACE, bool LAY, bool KEEP>
 __device__ __forceinline__ void decode_code(const Args& a, bool own_first)
 {
   using F = Family<IC, IV, W, DV>;
@@ -298,6 +301,26 @@ __device__ __forceinline__ void decode_code(const Args& a, bool own_first)
     if (pend_n == 0) return;
     bool valid = d < pend_n;
     if constexpr (MODE == MODE_EMIT) valid = valid && pf_key != KEY_NONE;
+    if constexpr (MODE == MODE_EMIT && KEEP) {
+      if (valid && a.trial_bits && pf_f < a.trial_bits_recs) {
+        // the winner's correction as the trial kernel kept it: written here,
+        // the task never enters the ring
+        // (G through an opaque copy, as in the finish code: no address of
+        // my items is kept across the decode loop)
+        int Gc = G;
+        asm volatile("" : "+s"(Gc));
+        const uint32_t ew = a.trial_bits[((long long)pf_f * a.n_trials + pf_ti) * Gc + q];
+        uint8_t* out = a.corrections + (long long)pf_shot * a.corr_stride + q;
+#pragma unroll 1
+        for (int k = 0; k < IV; ++k)
+          if ((vmask >> k) & 1u) out[Gc * k] = (uint8_t)((ew >> k) & 1u);
+        if (q == 0) {
+          a.converged[pf_shot] = 1;
+          a.iterations[pf_shot] = pf_miters + (int)(pf_key & ((1ull << KEY_ITER_BITS) - 1ull));
+        }
+        valid = false;
+      }
+    }
     if constexpr (MODE == MODE_CAND) valid = valid && pf_f >= 0;   // skipped by pruning
     // compact: rank of my entry among valid entries (count q == 0 lanes below)
     const unsigned long long vb = __ballot(valid && q == 0);
@@ -677,6 +700,10 @@ __device__ __forceinline__ void decode_code(const Args& a, bool own_first)
       } else if constexpr (MODE == MODE_CAND) {
         // weight of the undone correction e = e' + t over the slot
         const uint32_t w = group_reduce((uint32_t)__popc((hb ^ tbits) & vmask), G, OpAdd());
+        if constexpr (KEEP) {
+          if (fin && conv && a.trial_bits && rec < a.trial_bits_recs)
+            a.trial_bits[((long long)rec * a.n_trials + trial) * G + q] = (hb ^ tbits) & vmask;
+        }
         if (fin && q == 0) {
           st_iters += (unsigned long long)iter;
           if (conv) {
@@ -729,7 +756,7 @@ template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE, bool 
 __global__ __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu(min_waves_per_simd<Real, W, UL, TRACE, LAY>()))) void bpsf_kernel(Args a)
 {
-  decode_code<Real, IC, IV, W, DV, UL, MODE, TRACE, LAY>(a, true);
+  decode_code<Real, IC, IV, W, DV, UL, MODE, TRACE, LAY, true>(a, true);
 }
 
 // ------------------------------------------------------- mixed launches --
@@ -809,7 +836,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves_per_simd<Real, W, UL, false, false>
     }
     if (rem <= 0) continue;
     // (the mixed kernel counts taken tasks by the counter: no static chunk)
-    decode_code<Real, IC, IV, W, DV, UL, MODE, false, false>(m.code[c], false);
+    decode_code<Real, IC, IV, W, DV, UL, MODE, false, false, false>(m.code[c], false);
   }
 }
 

@@ -45,7 +45,11 @@ def test_bench_configuration_full_size():
     assert st["main_iterations"] == int(o32["main_iterations"].sum())
     # the oracle also runs the empty trial of every failed shot (cand_max_iter iterations each)
     assert st["trial_iterations"] == int(o32["trial_iterations"].sum()) - prm.cand_max_iter * st["failed_shots"]
-    assert st["rerun_iterations"] == int((o32["iterations"] - o32["main_iterations"])[won].sum())
+    # every failed shot's trials kept their corrections (25k records x 63
+    # trials x 8 lanes x 4 B fit the 256 MiB buffer): the last phase copied
+    # the winners' instead of re-running them; the winners' iteration counts
+    # are in the per-shot iterations compared above
+    assert st["rerun_iterations"] == 0 and int(won.sum()) > 0
     # every shot against the double oracle
     o64 = U.oracle_decode(code.hx, syn, 0.03, prm, precision="f64", threads=16)
     same = (g["correction"] == o64["correction"]).all(axis=1) & (g["converged"] == o64["converged"])

@@ -65,8 +65,13 @@ def test_mixed_five_codes_match_single_calls_and_oracle(precision, per):
         # padding after the code's N bits is left alone
         assert (out["correction"][sel, h.shape[1]:] == 7).all()
         st = out["stats"][c]
-        for f in ("main_iterations", "trial_iterations", "rerun_iterations", "failed_shots", "converged_trials"):
+        for f in ("main_iterations", "trial_iterations", "failed_shots", "converged_trials"):
             assert st[f] == one["stats"][f], (NAMES[c], f)
+        # a mixed call re-runs every winner (the single-code call copies the
+        # corrections its trials kept): the winners' trial iterations
+        won = o["winner"] >= 0
+        assert st["rerun_iterations"] == int((o["iterations"] - o["main_iterations"])[won].sum()) > 0, NAMES[c]
+        assert one["stats"]["rerun_iterations"] == 0
         assert st["errors"] == 0
 
 

@@ -37,8 +37,12 @@ def test_noalloc_equals_decode_two_calls():
             print(f"[[144]] {n} shots", flush=True)
             ref, got = _both(B, h, syn[:n], code.n, pri, bp)
             assert len(U.mismatches(got, ref)) == 0
-            assert got["stats"] == ref["stats"] and got["stats"]["failed_shots"] > 0
-            assert got["stats"]["errors"] == 0
+            # the fixed scratch keeps no trial corrections: its last phase
+            # re-runs the winners that the other call copies
+            assert ref["stats"]["rerun_iterations"] == 0 and got["stats"]["rerun_iterations"] > 0
+            same = {k: v for k, v in got["stats"].items() if k != "rerun_iterations"}
+            assert same == {k: v for k, v in ref["stats"].items() if k != "rerun_iterations"}
+            assert got["stats"]["failed_shots"] > 0 and got["stats"]["errors"] == 0
     finally:
         B.bpsf_free_code(h)
 
