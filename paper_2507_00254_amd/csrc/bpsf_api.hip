@@ -459,6 +459,7 @@ int fill_code_args(const bpsf_code_s* c, const bpsf_params* p, const TileDesc& t
 struct FixedScratch {
   void* base = nullptr;
   size_t bytes = 0;
+  bool keep = false;   // room past the records may hold kept trial corrections
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -472,16 +473,24 @@ constexpr size_t TRIAL_BITS_MAX = (size_t)256 << 20;
 // corrections, so the re-run phase copies those winners' corrections instead
 // of decoding up to cand_max_iter more iterations each: most of a small
 // call's tail, and the whole re-run phase of a call whose failed shots fit.
-// Not with the fixed scratch of bpsf_decode_noalloc.
-int keep_trial_bits(bpsf_code_s* c, const bpsf_params* p, int lanes, int64_t cap, const FixedScratch* fixed, Args* a)
+// With a fixed scratch, only in the room it leaves past the records when the
+// caller allows it (the request loop's single-code batches; not
+// bpsf_decode_noalloc).
+int keep_trial_bits(bpsf_code_s* c, const bpsf_params* p, int lanes, int64_t cap, const FixedScratch* fixed,
+                    size_t fixed_used, Args* a)
 {
-  if (fixed || p->k <= 0) return 0;
+  if (p->k <= 0 || (fixed && !fixed->keep)) return 0;
   const size_t per_rec = sizeof(uint32_t) * (size_t)(a->n_trials > 0 ? a->n_trials : 1) * (size_t)lanes;
-  const int64_t recs = std::min<int64_t>(cap, (int64_t)(TRIAL_BITS_MAX / per_rec));
+  const size_t room = fixed ? (fixed->bytes > fixed_used ? fixed->bytes - fixed_used : 0) : TRIAL_BITS_MAX;
+  const int64_t recs = std::min<int64_t>(cap, (int64_t)(room / per_rec));
   if (recs <= 0) return 0;
-  if (c->trial_bits.ensure(per_rec * (size_t)recs))
-    return fail(BPSF_ENOMEM, "trial corrections of %lld records", (long long)recs);
-  a->trial_bits = static_cast<uint32_t*>(c->trial_bits.p);
+  if (fixed) {
+    a->trial_bits = reinterpret_cast<uint32_t*>(static_cast<unsigned char*>(fixed->base) + fixed_used);
+  } else {
+    if (c->trial_bits.ensure(per_rec * (size_t)recs))
+      return fail(BPSF_ENOMEM, "trial corrections of %lld records", (long long)recs);
+    a->trial_bits = static_cast<uint32_t*>(c->trial_bits.p);
+  }
   a->trial_bits_recs = recs;
   return 0;
 }
@@ -512,8 +521,10 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl, con
   const size_t rec_bytes = sizeof(int32_t) * (size_t)a.rec_stride * (size_t)cap;
   const size_t key_bytes = sizeof(unsigned long long) * (size_t)cap;
   const size_t cnt_bytes = sizeof(unsigned long long) * CNT_WORDS;
+  size_t fixed_used = 0;
   if (fixed) {
     const size_t need = align256(cnt_bytes) + align256(key_bytes) + rec_bytes;
+    fixed_used = align256(need);
     if (need > fixed->bytes)
       return fail(BPSF_EINVAL, "%lld shots need %zu bytes of scratch; the fixed scratch holds %zu", (long long)shots,
                   need, fixed->bytes);
@@ -532,7 +543,7 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl, con
   const bool fp64 = p->precision == BPSF_PREC_FP64;
   if (c->sparse >= 0) {
     const SparseDesc d = sparse_desc(c->sparse);
-    if ((rc = keep_trial_bits(c, p, 64 * d.NW, cap, fixed, &a))) return rc;
+    if ((rc = keep_trial_bits(c, p, 64 * d.NW, cap, fixed, fixed_used, &a))) return rc;
     pl->lds = sparse_layout(c->sp_cells, c->M, d.NW, d.DVMAX, d.CPT).total;
     if (pl->lds > c->lds_max)
       return fail(BPSF_ENOTSUP, "the %d edges of this code need %zu bytes of LDS per workgroup, the device gives %zu",
@@ -559,7 +570,7 @@ int make_plan(bpsf_code_s* c, const bpsf_params* p, int64_t shots, Plan* pl, con
     }
     return 0;
   }
-  if ((rc = keep_trial_bits(c, p, 64 / t.D, cap, fixed, &a))) return rc;
+  if ((rc = keep_trial_bits(c, p, 64 / t.D, cap, fixed, fixed_used, &a))) return rc;
   pl->lds = tile_lds(c, t, fp64, c->uniform, layered);
   if (pl->lds > c->lds_max)
     return fail(BPSF_ENOTSUP, "this tile needs %zu bytes of LDS per workgroup, the device gives %zu", pl->lds,
@@ -1278,7 +1289,8 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
     int per_cu = 0;
     if (occupancy(true, TileDesc{fam, 0}, fp64, uniform, mode, lds, nullptr, &ma, &per_cu))
       return fail(BPSF_EDEVICE, "occupancy query failed for mode %d", mode);
-    grid[mode] = per_cu * m->codes[0]->cus;
+    // the mixed kernel keeps its per-code wave counts in 16 bits
+    grid[mode] = std::min(per_cu * m->codes[0]->cus, 65535);
   }
   if (reset_counters(cnt, (int)words, stream)) return fail(BPSF_EDEVICE, "counter reset launch");
   if (!counts && bucket_launch(b, stream)) return fail(BPSF_EDEVICE, "bucketing launch failed");
@@ -1529,6 +1541,7 @@ int bpsf::decode_in(bpsf_code c, const uint8_t* syndromes, const double* priors,
   FixedScratch fx;
   fx.base = scratch;
   fx.bytes = scratch_bytes;
+  fx.keep = true;   // the request loop leaves room for kept trial corrections
   return decode_call(c, syndromes, priors, shots, p, corrections, converged, iterations, stream, &fx);
 }
 

@@ -46,13 +46,15 @@ namespace bpsf {
 // left and returns once its slots have drained. UL: every bit has the same
 // channel LLR (uniform priors), held in a scalar. LAY: layered schedule (the
 // checks layer by layer, each reading and updating the bits' posteriors)
-// instead of flooding. own_first: the wave's first chunk of tasks follows
-// from its block index instead of the shared counter.
+// instead of flooding. first, n_first: n_first waves of the launch take
+// their first chunk of tasks without the shared counter, this wave chunk
+// `first` of them (-1: none), and the counter hands out the chunks after
+// those n_first.
 // KEEP: the launch may keep trial corrections (Args::trial_bits), which a
 // single-code launch does and a mixed launch never does (the code is then
 // left out of the mixed kernel, whose registers are tighter)
 template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE, bool TRACE, bool LAY, bool KEEP>
-__device__ __forceinline__ void decode_code(const Args& a, bool own_first)
+__device__ __forceinline__ void decode_code(const Args& a, int first, int n_first)
 {
   using F = Family<IC, IV, W, DV>;
   using R = RT<Real>;
@@ -104,12 +106,15 @@ __device__ __forceinline__ void decode_code(const Args& a, bool own_first)
     next_ctr = &a.counters[CNT_EMIT_NEXT];
   }
   n_tasks = bcast0ll(n_tasks);
-  // own_first: wave b's first chunk is tasks [b * chunk, (b + 1) * chunk)
-  // and the counter hands out the rest after gridDim.x chunks, so a wave with
+  // a wave's own first chunk is tasks [first * chunk, (first + 1) * chunk)
+  // and the counter hands out the rest after n_first chunks, so a wave with
   // nothing to do leaves before touching LDS or the counter (small calls
   // launch many such waves)
-  if (own_first && (long long)blockIdx.x * a.chunk >= n_tasks) return;
-  bool first_chunk = own_first;
+  first = __builtin_amdgcn_readfirstlane(first);   // wave-uniform
+  n_first = __builtin_amdgcn_readfirstlane(n_first);
+  if (first >= 0 && (long long)first * a.chunk >= n_tasks) return;
+  if (first < 0 && (long long)n_first * a.chunk >= n_tasks) return;
+  bool first_chunk = first >= 0;
 
   // ---- per-code tables into LDS ------------------------------------------
   __syncthreads();   // a previous code's phase may still be reading them
@@ -228,12 +233,12 @@ __device__ __forceinline__ void decode_code(const Args& a, bool own_first)
     if (cnext >= cend) {
       long long base = 0;
       if (first_chunk) {
-        base = (long long)blockIdx.x * a.chunk;
+        base = (long long)first * a.chunk;
         first_chunk = false;
       } else {
         if (lane == 0) base = (long long)atomicAdd(next_ctr, (unsigned long long)a.chunk);
         base = bcast0ll(base);
-        if (own_first) base += (long long)gridDim.x * a.chunk;
+        if (n_first > 0) base += (long long)n_first * a.chunk;
       }
       if (base >= n_tasks) { exhausted = true; return; }
       cnext = base;
@@ -756,7 +761,9 @@ template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE, bool 
 __global__ __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu(min_waves_per_simd<Real, W, UL, TRACE, LAY>()))) void bpsf_kernel(Args a)
 {
-  decode_code<Real, IC, IV, W, DV, UL, MODE, TRACE, LAY, true>(a, true);
+  const int b = (int)blockIdx.x;
+  __builtin_assume(b >= 0);
+  decode_code<Real, IC, IV, W, DV, UL, MODE, TRACE, LAY, true>(a, b, (int)gridDim.x);
 }
 
 // ------------------------------------------------------- mixed launches --
@@ -783,60 +790,79 @@ __device__ __forceinline__ long long phase_tasks(const Args& a)
 // One phase over several codes of one family: every wave starts on the code
 // under the point (b + 1/2) / grid of the cumulative estimated work and then
 // takes the codes after it in turn, so waves whose code runs out help the
-// others.
+// others. The waves that start on a code take their first chunk of its tasks
+// by their rank among those waves, not from the code's counter: a small call
+// launches far more waves than it has chunks, and every counter atomic of a
+// wave that finds nothing costs the others a round trip on the same word.
 template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE>
 __global__ __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu(min_waves_per_simd<Real, W, UL, false, false>()))) void bpsf_mixed_kernel(const MixArgs m)
 {
-  // every code's task and taken counts in one round trip: lane c loads code c's
+  // every code's task count in one round trip: lane c loads code c's
   const int lane = threadIdx.x;
-  long long tasks = 0, taken = 0;
-  if (lane < m.n_codes) {
-    tasks = phase_tasks<MODE>(m.code[lane]);
-    taken = phase_taken<MODE>(m.code[lane]);
-  }
+  long long tasks = 0;
+  if (lane < m.n_codes) tasks = phase_tasks<MODE>(m.code[lane]);
   float w[MIX_MAX_CODES];
-  long long ntask[MIX_MAX_CODES], left[MIX_MAX_CODES];
   float total = 0.f;
 #pragma unroll
   for (int c = 0; c < MIX_MAX_CODES; ++c) {
     const long long tc = ((long long)__builtin_amdgcn_readlane((int)(tasks >> 32), c) << 32) |
                          (unsigned int)__builtin_amdgcn_readlane((int)(tasks & 0xffffffff), c);
-    const long long tk = ((long long)__builtin_amdgcn_readlane((int)(taken >> 32), c) << 32) |
-                         (unsigned int)__builtin_amdgcn_readlane((int)(taken & 0xffffffff), c);
     w[c] = c < m.n_codes ? (float)tc * m.cost[c] : 0.f;
-    ntask[c] = tc;
-    left[c] = c < m.n_codes ? tc - tk : 0;
     total += w[c];
   }
-  const float at = ((float)blockIdx.x + 0.5f) / (float)gridDim.x * total;
-  int c0 = 0;
-  float acc = 0.f;
+  // code c (with work) starts the waves whose point lies in [P_c, P_c + w_c),
+  // P_c the work of the codes before it: waves [lo_c, lo_c + nw_c) (the
+  // launch holds fewer than 2^16 waves: nw_c is kept in 16 bits)
+  auto point = [&](int b) { return ((float)b + 0.5f) / (float)gridDim.x * total; };
+  auto first_at = [&](float x) {   // first wave whose point is at or past x
+    int lo = 0, hi = (int)gridDim.x;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (point(mid) >= x) hi = mid;
+      else lo = mid + 1;
+    }
+    return lo;
+  };
+  int lo_w[MIX_MAX_CODES], nw[MIX_MAX_CODES];
+  float pc = 0.f;
 #pragma unroll
   for (int c = 0; c < MIX_MAX_CODES; ++c) {
-    if (acc > at || w[c] <= 0.f) continue;
-    c0 = c;
-    acc += w[c];
+    lo_w[c] = w[c] > 0.f ? first_at(pc) : 0;
+    pc += w[c];
+  }
+  int next_lo = (int)gridDim.x;
+#pragma unroll
+  for (int c = MIX_MAX_CODES - 1; c >= 0; --c) {
+    nw[c] = w[c] > 0.f ? next_lo - lo_w[c] : 0;
+    if (w[c] > 0.f) next_lo = lo_w[c];
+  }
+  const int b = (int)blockIdx.x;
+  // kept across the codes' decodes in one vector register, lane c holding
+  // nw_c (scalar registers are the scarce ones here)
+  int c0 = 0, r0 = -1, nw_lane = 0;
+#pragma unroll
+  for (int c = 0; c < MIX_MAX_CODES; ++c) {
+    if (nw[c] > 0 && b >= lo_w[c] && b < lo_w[c] + nw[c]) {
+      c0 = c;
+      r0 = b - lo_w[c];
+    }
+    if (lane == c) nw_lane = nw[c];
   }
   for (int i = 0; i < m.n_codes; ++i) {
     const int c = (c0 + i) % m.n_codes;
-    // skip the table set-up of a code whose tasks are all taken (counts read
-    // afresh for every code after the first)
-    long long rem = 0, nt = 0;
-#pragma unroll
-    for (int cc = 0; cc < MIX_MAX_CODES; ++cc)
-      if (cc == c) {
-        rem = left[cc];
-        nt = ntask[cc];
+    const int nf = __builtin_amdgcn_readlane(nw_lane, c);
+    if (i > 0) {
+      // skip the table set-up of a code whose tasks are all taken: its
+      // waves' first chunks and what its counter has handed out (read afresh)
+      long long t = 0, nt = 0;
+      if (lane == 0) {
+        t = phase_taken<MODE>(m.code[c]);
+        nt = phase_tasks<MODE>(m.code[c]);
       }
-    if (i > 0 && rem > 0) {
-      long long t = 0;
-      if (lane == 0) t = phase_taken<MODE>(m.code[c]);
-      rem = nt - bcast0ll(t);
+      if (bcast0ll(nt) - bcast0ll(t) - (long long)nf * m.code[c].chunk <= 0) continue;
     }
-    if (rem <= 0) continue;
-    // (the mixed kernel counts taken tasks by the counter: no static chunk)
-    decode_code<Real, IC, IV, W, DV, UL, MODE, false, false, false>(m.code[c], false);
+    decode_code<Real, IC, IV, W, DV, UL, MODE, false, false, false>(m.code[c], i == 0 ? r0 : -1, nf);
   }
 }
 

@@ -160,6 +160,7 @@ struct bpsf_server_s {
   int64_t cap = 0;            // shots per batch at most (the caller's limit)
   int64_t max_request = 0;    // the largest request the pool can ever hold (<= cap)
   int scratch_stride = 0;     // record words per shot of a batch's decode scratch
+  size_t keep_bytes = 0;      // room per batch for kept trial corrections (batched mode)
   void* pool_mem = nullptr;
   Pool pool;
   std::vector<Lane> lanes;
@@ -193,11 +194,20 @@ BatchLayout layout_of(const bpsf_server_s* s, int64_t n, size_t scratch)
   return L;
 }
 
-// The device bytes of a batch of n shots (its scratch: the mixed decode's
-// in batched mode; per-request decodes use their code's own scratch).
+// Room a batched-mode batch adds to its scratch for the corrections that a
+// single-code batch's trials keep (the last phase then copies the winners'
+// instead of decoding them again; 1 MiB keeps about 130 records of a
+// 63-trial small-family decode, every failed shot of a small batch): at most
+// a sixteenth of a caller's device budget.
+constexpr size_t KEEP_BYTES = (size_t)1 << 20;
+
+// The device bytes of a batch of n shots (its scratch: the mixed decode's,
+// and room for kept trial corrections, in batched mode; per-request decodes
+// use their code's own scratch).
 int batch_layout(bpsf_server_s* s, int64_t n, BatchLayout* out)
 {
-  const size_t scratch = s->batching ? bpsf::mix_scratch_size(s->n_codes, n, s->scratch_stride) : 0;
+  const size_t scratch =
+      s->batching ? bpsf::mix_scratch_size(s->n_codes, n, s->scratch_stride) + s->keep_bytes : 0;
   *out = layout_of(s, n, scratch);
   return 0;
 }
@@ -645,6 +655,7 @@ int bpsf_server_create(const bpsf_code* codes, int32_t n_codes, const double* co
     rc = bpsf::mix_scratch_stride(s->lanes[0].mix, &s->params, &s->scratch_stride);
     if (rc) rc = sfail(rc, "scratch of a batch: %s", bpsf_last_error());
   }
+  s->keep_bytes = device_budget_bytes > 0 ? std::min(KEEP_BYTES, al256((size_t)device_budget_bytes / 16)) : KEEP_BYTES;
   BatchLayout full;
   if (!rc) rc = batch_layout(s, s->cap, &full);
   size_t budget = 0;
