@@ -597,6 +597,7 @@ struct bpsf_mix_s {
   DevBuf rec_lists;  // [n][shots] int32 record indices of each code
   DevBuf records, keys;
   DevBuf counters;   // [n][CNT_WORDS] per code, then the mix words below
+  DevBuf trial_bits; // kept corrections of converged trials, a region per code
   unsigned long long* last_counters = nullptr;   // counters of the last call (its scratch)
   std::mutex mu;
 };
@@ -1258,6 +1259,38 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
     a.keys = static_cast<unsigned long long*>(keys);
     a.counters = cnt + (size_t)CNT_WORDS * i;
   }
+  // kept trial corrections: the codes share the record numbers, and each
+  // code's decodes have lanes of their own, so every code keeps the same
+  // first records in a region of its own (with a fixed scratch, in the room
+  // past the call's when the caller allows it)
+  if (p->k > 0 && (!fixed || fixed->keep)) {
+    size_t per_rec[MIX_MAX_CODES] = {}, sum = 0;
+    for (int i = 0; i < m->n; ++i)
+      if (!counts || counts[i] > 0) {
+        const Args& a = ma.code[i];
+        per_rec[i] = sizeof(uint32_t) * (size_t)(a.n_trials > 0 ? a.n_trials : 1) * (size_t)(64 / tiles[i].D);
+        sum += per_rec[i];
+      }
+    const size_t used = fixed ? align256(mix_fixed_bytes(m->n, shots, stride)) : 0;
+    const size_t room = fixed ? (fixed->bytes > used ? fixed->bytes - used : 0) : TRIAL_BITS_MAX;
+    const int64_t recs = sum ? std::min<int64_t>(shots, (int64_t)(room / sum)) : 0;
+    if (recs > 0) {
+      unsigned char* kb = nullptr;
+      if (fixed) {
+        kb = static_cast<unsigned char*>(fixed->base) + used;
+      } else {
+        if (m->trial_bits.ensure(sum * (size_t)recs))
+          return fail(BPSF_ENOMEM, "trial corrections of %lld records", (long long)recs);
+        kb = static_cast<unsigned char*>(m->trial_bits.p);
+      }
+      for (int i = 0; i < m->n; ++i) {
+        if (!per_rec[i]) continue;
+        ma.code[i].trial_bits = reinterpret_cast<uint32_t*>(kb);
+        ma.code[i].trial_bits_recs = recs;
+        kb += per_rec[i] * (size_t)recs;
+      }
+    }
+  }
   BucketArgs b;
   memset(&b, 0, sizeof b);
   b.shot_code = shot_code;
@@ -1587,6 +1620,7 @@ int bpsf::mix_decode_grouped_in(bpsf_mix m, const int64_t* counts, const uint8_t
   FixedScratch fx;
   fx.base = scratch;
   fx.bytes = scratch_bytes;
+  fx.keep = true;   // the request loop leaves room for kept trial corrections
   return mix_decode(m, nullptr, counts, syndromes, syn_stride, priors, shots, p, corrections, corr_stride, converged,
                     iterations, stream, &fx);
 }

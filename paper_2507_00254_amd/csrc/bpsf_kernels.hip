@@ -50,9 +50,8 @@ namespace bpsf {
 // their first chunk of tasks without the shared counter, this wave chunk
 // `first` of them (-1: none), and the counter hands out the chunks after
 // those n_first.
-// KEEP: the launch may keep trial corrections (Args::trial_bits), which a
-// single-code launch does and a mixed launch never does (the code is then
-// left out of the mixed kernel, whose registers are tighter)
+// KEEP: the launch may keep trial corrections (Args::trial_bits); without
+// it the code that writes and copies them is left out.
 template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE, bool TRACE, bool LAY, bool KEEP>
 __device__ __forceinline__ void decode_code(const Args& a, int first, int n_first)
 {
@@ -862,7 +861,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves_per_simd<Real, W, UL, false, false>
       }
       if (bcast0ll(nt) - bcast0ll(t) - (long long)nf * m.code[c].chunk <= 0) continue;
     }
-    decode_code<Real, IC, IV, W, DV, UL, MODE, false, false, false>(m.code[c], i == 0 ? r0 : -1, nf);
+    decode_code<Real, IC, IV, W, DV, UL, MODE, false, false, true>(m.code[c], i == 0 ? r0 : -1, nf);
   }
 }
 

@@ -67,12 +67,40 @@ def test_mixed_five_codes_match_single_calls_and_oracle(precision, per):
         st = out["stats"][c]
         for f in ("main_iterations", "trial_iterations", "failed_shots", "converged_trials"):
             assert st[f] == one["stats"][f], (NAMES[c], f)
-        # a mixed call re-runs every winner (the single-code call copies the
-        # corrections its trials kept): the winners' trial iterations
+        # the winners of the kept records are copied, the others decoded again
+        # (which records a code's failed shots get depends on the order the
+        # waves reach them): at most every winner's trial iterations
         won = o["winner"] >= 0
-        assert st["rerun_iterations"] == int((o["iterations"] - o["main_iterations"])[won].sum()) > 0, NAMES[c]
+        assert 0 <= st["rerun_iterations"] <= int((o["iterations"] - o["main_iterations"])[won].sum()), NAMES[c]
         assert one["stats"]["rerun_iterations"] == 0
         assert st["errors"] == 0
+
+
+def test_mixed_kept_corrections_run_out():
+    """More failed shots than the kept records of a mixed call hold: the
+    winners of the first records are copied, the rest decoded again, and
+    every shot equals the single-code call's (which keeps all of its
+    records)."""
+    p = 0.08
+    hs = [codes.get_code(n).hx for n in NAMES]
+    sc, syn, _, _ = shots.mixed_batch(hs, p, 3000, shots.stream_key(shots.MASTER_SEED, 905))
+    prm = U.oracle_params(k=8)          # 256 trials: a few thousand records fill the kept region
+    print(f"mixed f32 {len(sc)} shots", flush=True)
+    out = _mix_decode(hs, sc, syn, [np.full(h.shape[1], p) for h in hs], prm)
+    assert out["bad"] == 0
+    failed = rerun = 0
+    for c, h in enumerate(hs):
+        g, sel = _per_code(out, sc, c, h.shape[1])
+        one = U.gpu_decode(h, syn[sel, :h.shape[0]], p, prm)
+        assert len(U.mismatches(g, one)) == 0, NAMES[c]
+        st = out["stats"][c]
+        for f in ("main_iterations", "trial_iterations", "failed_shots", "converged_trials", "errors"):
+            assert st[f] == one["stats"][f], (NAMES[c], f)
+        assert one["stats"]["rerun_iterations"] == 0
+        failed += st["failed_shots"]
+        rerun += st["rerun_iterations"]
+    print(f"failed shots {failed}, re-run iterations {rerun}", flush=True)
+    assert rerun > 0
 
 
 def test_mixed_first_success_with_pruning():
