@@ -95,12 +95,13 @@ typedef struct {
                                 the failed first BP) unless FORCE_PP or NO_EARLY_STOP is set
                                 or cand_max_iter > max_iter */
   int64_t rerun_iterations;  /* iterations of the re-runs that emit winning trials; in calls of
-                                the one-wave and sparse families (bpsf_decode, bpsf_mix_*, the
-                                request loop's batches) the trials of the first failed shots (as
-                                many as 256 MiB of kept corrections cover, 4 B per lane of a decode
-                                per trial and code; 1 MiB per batch of the request loop) keep their
-                                corrections and their winners are copied, not re-run; the wide
-                                family and bpsf_decode_noalloc re-run every winner */
+                                the one-wave and sparse families (bpsf_decode, bpsf_mix_* calls of
+                                at most 65536 shots, the request loop's batches) the trials of the
+                                first failed shots (as many as 256 MiB of kept corrections cover,
+                                4 B per lane of a decode per trial and code; 1 MiB per batch of the
+                                request loop) keep their corrections and their winners are copied,
+                                not re-run; the wide family, larger mixed calls and
+                                bpsf_decode_noalloc re-run every winner */
   int64_t failed_shots;      /* shots whose first BP failed (or all shots with FORCE_PP, k > 0) */
   int64_t converged_trials;  /* trials that reproduced their syndrome */
   int64_t errors;            /* internal consistency failures (must be 0) */

@@ -60,11 +60,19 @@ struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   ~DevBuf() { if (p) (void)hipFree(p); }
-  // grow-only; contents are not preserved
-  int ensure(size_t want)
+  // grow-only, by at least half again and to at least 1 MiB (at most `most`
+  // unless `want` is more), so calls whose sizes creep up reallocate (and
+  // wait for the device to free the old buffer) only a few times; contents
+  // are not preserved
+  int ensure(size_t want, size_t most = SIZE_MAX)
   {
     if (want <= bytes) return 0;
+    const size_t grown = std::max(want, std::min(std::max(bytes + bytes / 2, (size_t)1 << 20), most));
     if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
+    if (grown > want && hipMalloc(&p, grown) == hipSuccess) {
+      bytes = grown;
+      return 0;
+    }
     if (hipMalloc(&p, want) != hipSuccess) { p = nullptr; return -1; }
     bytes = want;
     return 0;
@@ -346,14 +354,14 @@ int update_masks(bpsf_code_s* c, const bpsf_params* p, void* stream)
 // Resident blocks per CU of a kernel at an LDS size (memoized: the answer
 // depends only on the kernel, the LDS bytes and the device).
 int occupancy(bool mixed, const TileDesc& t, bool fp64, bool uniform, int mode, size_t lds, const Args* a,
-              const MixArgs* m, int* out, bool layered = false)
+              const MixArgs* m, int* out, bool layered = false, bool small_mix = false)
 {
   static std::mutex mu;
   static std::map<std::tuple<int, int, int, int, int, int, size_t, int>, int> memo;
   int dev = 0;
   (void)hipGetDevice(&dev);
-  const auto key = std::make_tuple(dev, (int)mixed, t.fam, mixed ? 0 : t.D, (int)fp64 * 2 + (int)uniform, mode, lds,
-                                   (int)layered);
+  const auto key = std::make_tuple(dev, (int)mixed, t.fam, mixed ? (int)small_mix : t.D, (int)fp64 * 2 + (int)uniform,
+                                   mode, lds, (int)layered);
   {
     std::lock_guard<std::mutex> lk(mu);
     auto it = memo.find(key);
@@ -363,7 +371,7 @@ int occupancy(bool mixed, const TileDesc& t, bool fp64, bool uniform, int mode, 
     }
   }
   int n = 0;
-  const int rc = mixed ? mixed_dispatch(1, t.fam, fp64, uniform, mode, *m, lds, 0, nullptr, &n)
+  const int rc = mixed ? mixed_dispatch(1, t.fam, fp64, uniform, small_mix, mode, *m, lds, 0, nullptr, &n)
                        : tile_dispatch(1, t, fp64, uniform, mode, false, *a, lds, 0, nullptr, &n, layered);
   if (rc || n < 1) return -1;
   std::lock_guard<std::mutex> lk(mu);
@@ -487,7 +495,7 @@ int keep_trial_bits(bpsf_code_s* c, const bpsf_params* p, int lanes, int64_t cap
   if (fixed) {
     a->trial_bits = reinterpret_cast<uint32_t*>(static_cast<unsigned char*>(fixed->base) + fixed_used);
   } else {
-    if (c->trial_bits.ensure(per_rec * (size_t)recs))
+    if (c->trial_bits.ensure(per_rec * (size_t)recs, TRIAL_BITS_MAX))
       return fail(BPSF_ENOMEM, "trial corrections of %lld records", (long long)recs);
     a->trial_bits = static_cast<uint32_t*>(c->trial_bits.p);
   }
@@ -1259,11 +1267,13 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
     a.keys = static_cast<unsigned long long*>(keys);
     a.counters = cnt + (size_t)CNT_WORDS * i;
   }
-  // kept trial corrections: the codes share the record numbers, and each
+  // kept trial corrections (calls of the mixed kernel's small form, and
+  // grouped calls of one code): the codes share the record numbers, and each
   // code's decodes have lanes of their own, so every code keeps the same
   // first records in a region of its own (with a fixed scratch, in the room
   // past the call's when the caller allows it)
-  if (p->k > 0 && (!fixed || fixed->keep)) {
+  const bool small_form = shots <= SMALL_CALL_SHOTS;
+  if (p->k > 0 && (!fixed || fixed->keep) && (small_form || only >= 0)) {
     size_t per_rec[MIX_MAX_CODES] = {}, sum = 0;
     for (int i = 0; i < m->n; ++i)
       if (!counts || counts[i] > 0) {
@@ -1279,7 +1289,7 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
       if (fixed) {
         kb = static_cast<unsigned char*>(fixed->base) + used;
       } else {
-        if (m->trial_bits.ensure(sum * (size_t)recs))
+        if (m->trial_bits.ensure(sum * (size_t)recs, TRIAL_BITS_MAX))
           return fail(BPSF_ENOMEM, "trial corrections of %lld records", (long long)recs);
         kb = static_cast<unsigned char*>(m->trial_bits.p);
       }
@@ -1320,19 +1330,19 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
   int grid[3];
   for (int mode = 0; mode < 3; ++mode) {
     int per_cu = 0;
-    if (occupancy(true, TileDesc{fam, 0}, fp64, uniform, mode, lds, nullptr, &ma, &per_cu))
+    if (occupancy(true, TileDesc{fam, 0}, fp64, uniform, mode, lds, nullptr, &ma, &per_cu, false, small_form))
       return fail(BPSF_EDEVICE, "occupancy query failed for mode %d", mode);
     // the mixed kernel keeps its per-code wave counts in 16 bits
     grid[mode] = std::min(per_cu * m->codes[0]->cus, 65535);
   }
   if (reset_counters(cnt, (int)words, stream)) return fail(BPSF_EDEVICE, "counter reset launch");
   if (!counts && bucket_launch(b, stream)) return fail(BPSF_EDEVICE, "bucketing launch failed");
-  if (mixed_dispatch(0, fam, fp64, uniform, MODE_MAIN, ma, lds, grid[MODE_MAIN], stream, nullptr))
+  if (mixed_dispatch(0, fam, fp64, uniform, small_form, MODE_MAIN, ma, lds, grid[MODE_MAIN], stream, nullptr))
     return fail(BPSF_EDEVICE, "first-BP launch failed");
   if (p->k > 0) {
-    if (mixed_dispatch(0, fam, fp64, uniform, MODE_CAND, ma, lds, grid[MODE_CAND], stream, nullptr))
+    if (mixed_dispatch(0, fam, fp64, uniform, small_form, MODE_CAND, ma, lds, grid[MODE_CAND], stream, nullptr))
       return fail(BPSF_EDEVICE, "trial launch failed");
-    if (mixed_dispatch(0, fam, fp64, uniform, MODE_EMIT, ma, lds, grid[MODE_EMIT], stream, nullptr))
+    if (mixed_dispatch(0, fam, fp64, uniform, small_form, MODE_EMIT, ma, lds, grid[MODE_EMIT], stream, nullptr))
       return fail(BPSF_EDEVICE, "re-run launch failed");
   }
   return 0;

@@ -789,79 +789,136 @@ __device__ __forceinline__ long long phase_tasks(const Args& a)
 // One phase over several codes of one family: every wave starts on the code
 // under the point (b + 1/2) / grid of the cumulative estimated work and then
 // takes the codes after it in turn, so waves whose code runs out help the
-// others. The waves that start on a code take their first chunk of its tasks
-// by their rank among those waves, not from the code's counter: a small call
-// launches far more waves than it has chunks, and every counter atomic of a
-// wave that finds nothing costs the others a round trip on the same word.
-template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE>
+// others.
+// SMALL (calls of at most 65536 shots): the waves that start on a code take
+// their first chunk of its tasks by their rank among those waves, not from
+// the code's counter (a small call launches far more waves than it has
+// chunks, and every counter atomic of a wave that finds nothing costs the
+// others a round trip on the same word), and the trials keep their
+// corrections. Larger calls take every chunk from the counters and keep no
+// corrections: that form's registers leave their long phases about 2%
+// faster.
+template <typename Real, int IC, int IV, int W, int DV, bool UL, int MODE, bool SMALL>
 __global__ __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu(min_waves_per_simd<Real, W, UL, false, false>()))) void bpsf_mixed_kernel(const MixArgs m)
 {
-  // every code's task count in one round trip: lane c loads code c's
-  const int lane = threadIdx.x;
-  long long tasks = 0;
-  if (lane < m.n_codes) tasks = phase_tasks<MODE>(m.code[lane]);
-  float w[MIX_MAX_CODES];
-  float total = 0.f;
+  if constexpr (SMALL) {
+    // every code's task count in one round trip: lane c loads code c's
+    const int lane = threadIdx.x;
+    long long tasks = 0;
+    if (lane < m.n_codes) tasks = phase_tasks<MODE>(m.code[lane]);
+    float w[MIX_MAX_CODES];
+    float total = 0.f;
 #pragma unroll
-  for (int c = 0; c < MIX_MAX_CODES; ++c) {
-    const long long tc = ((long long)__builtin_amdgcn_readlane((int)(tasks >> 32), c) << 32) |
-                         (unsigned int)__builtin_amdgcn_readlane((int)(tasks & 0xffffffff), c);
-    w[c] = c < m.n_codes ? (float)tc * m.cost[c] : 0.f;
-    total += w[c];
-  }
-  // code c (with work) starts the waves whose point lies in [P_c, P_c + w_c),
-  // P_c the work of the codes before it: waves [lo_c, lo_c + nw_c) (the
-  // launch holds fewer than 2^16 waves: nw_c is kept in 16 bits)
-  auto point = [&](int b) { return ((float)b + 0.5f) / (float)gridDim.x * total; };
-  auto first_at = [&](float x) {   // first wave whose point is at or past x
-    int lo = 0, hi = (int)gridDim.x;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (point(mid) >= x) hi = mid;
-      else lo = mid + 1;
+    for (int c = 0; c < MIX_MAX_CODES; ++c) {
+      const long long tc = ((long long)__builtin_amdgcn_readlane((int)(tasks >> 32), c) << 32) |
+                           (unsigned int)__builtin_amdgcn_readlane((int)(tasks & 0xffffffff), c);
+      w[c] = c < m.n_codes ? (float)tc * m.cost[c] : 0.f;
+      total += w[c];
     }
-    return lo;
-  };
-  int lo_w[MIX_MAX_CODES], nw[MIX_MAX_CODES];
-  float pc = 0.f;
-#pragma unroll
-  for (int c = 0; c < MIX_MAX_CODES; ++c) {
-    lo_w[c] = w[c] > 0.f ? first_at(pc) : 0;
-    pc += w[c];
-  }
-  int next_lo = (int)gridDim.x;
-#pragma unroll
-  for (int c = MIX_MAX_CODES - 1; c >= 0; --c) {
-    nw[c] = w[c] > 0.f ? next_lo - lo_w[c] : 0;
-    if (w[c] > 0.f) next_lo = lo_w[c];
-  }
-  const int b = (int)blockIdx.x;
-  // kept across the codes' decodes in one vector register, lane c holding
-  // nw_c (scalar registers are the scarce ones here)
-  int c0 = 0, r0 = -1, nw_lane = 0;
-#pragma unroll
-  for (int c = 0; c < MIX_MAX_CODES; ++c) {
-    if (nw[c] > 0 && b >= lo_w[c] && b < lo_w[c] + nw[c]) {
-      c0 = c;
-      r0 = b - lo_w[c];
-    }
-    if (lane == c) nw_lane = nw[c];
-  }
-  for (int i = 0; i < m.n_codes; ++i) {
-    const int c = (c0 + i) % m.n_codes;
-    const int nf = __builtin_amdgcn_readlane(nw_lane, c);
-    if (i > 0) {
-      // skip the table set-up of a code whose tasks are all taken: its
-      // waves' first chunks and what its counter has handed out (read afresh)
-      long long t = 0, nt = 0;
-      if (lane == 0) {
-        t = phase_taken<MODE>(m.code[c]);
-        nt = phase_tasks<MODE>(m.code[c]);
+    // code c (with work) starts the waves whose point lies in [P_c, P_c + w_c),
+    // P_c the work of the codes before it: waves [lo_c, lo_c + nw_c) (the
+    // launch holds fewer than 2^16 waves: nw_c is kept in 16 bits)
+    auto point = [&](int b) { return ((float)b + 0.5f) / (float)gridDim.x * total; };
+    auto first_at = [&](float x) {   // first wave whose point is at or past x
+      int lo = 0, hi = (int)gridDim.x;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (point(mid) >= x) hi = mid;
+        else lo = mid + 1;
       }
-      if (bcast0ll(nt) - bcast0ll(t) - (long long)nf * m.code[c].chunk <= 0) continue;
+      return lo;
+    };
+    int lo_w[MIX_MAX_CODES], nw[MIX_MAX_CODES];
+    float pc = 0.f;
+#pragma unroll
+    for (int c = 0; c < MIX_MAX_CODES; ++c) {
+      lo_w[c] = w[c] > 0.f ? first_at(pc) : 0;
+      pc += w[c];
     }
-    decode_code<Real, IC, IV, W, DV, UL, MODE, false, false, true>(m.code[c], i == 0 ? r0 : -1, nf);
+    int next_lo = (int)gridDim.x;
+#pragma unroll
+    for (int c = MIX_MAX_CODES - 1; c >= 0; --c) {
+      nw[c] = w[c] > 0.f ? next_lo - lo_w[c] : 0;
+      if (w[c] > 0.f) next_lo = lo_w[c];
+    }
+    const int b = (int)blockIdx.x;
+    // kept across the codes' decodes in one vector register, lane c holding
+    // nw_c (scalar registers are the scarce ones here)
+    int c0 = 0, r0 = -1, nw_lane = 0;
+#pragma unroll
+    for (int c = 0; c < MIX_MAX_CODES; ++c) {
+      if (nw[c] > 0 && b >= lo_w[c] && b < lo_w[c] + nw[c]) {
+        c0 = c;
+        r0 = b - lo_w[c];
+      }
+      if (lane == c) nw_lane = nw[c];
+    }
+    for (int i = 0; i < m.n_codes; ++i) {
+      const int c = (c0 + i) % m.n_codes;
+      const int nf = __builtin_amdgcn_readlane(nw_lane, c);
+      if (i > 0) {
+        // skip the table set-up of a code whose tasks are all taken: its
+        // waves' first chunks and what its counter has handed out (read afresh)
+        long long t = 0, nt = 0;
+        if (lane == 0) {
+          t = phase_taken<MODE>(m.code[c]);
+          nt = phase_tasks<MODE>(m.code[c]);
+        }
+        if (bcast0ll(nt) - bcast0ll(t) - (long long)nf * m.code[c].chunk <= 0) continue;
+      }
+      decode_code<Real, IC, IV, W, DV, UL, MODE, false, false, true>(m.code[c], i == 0 ? r0 : -1, nf);
+    }
+  } else {
+    // every code's task and taken counts in one round trip: lane c loads code c's
+    const int lane = threadIdx.x;
+    long long tasks = 0, taken = 0;
+    if (lane < m.n_codes) {
+      tasks = phase_tasks<MODE>(m.code[lane]);
+      taken = phase_taken<MODE>(m.code[lane]);
+    }
+    float w[MIX_MAX_CODES];
+    long long ntask[MIX_MAX_CODES], left[MIX_MAX_CODES];
+    float total = 0.f;
+#pragma unroll
+    for (int c = 0; c < MIX_MAX_CODES; ++c) {
+      const long long tc = ((long long)__builtin_amdgcn_readlane((int)(tasks >> 32), c) << 32) |
+                           (unsigned int)__builtin_amdgcn_readlane((int)(tasks & 0xffffffff), c);
+      const long long tk = ((long long)__builtin_amdgcn_readlane((int)(taken >> 32), c) << 32) |
+                           (unsigned int)__builtin_amdgcn_readlane((int)(taken & 0xffffffff), c);
+      w[c] = c < m.n_codes ? (float)tc * m.cost[c] : 0.f;
+      ntask[c] = tc;
+      left[c] = c < m.n_codes ? tc - tk : 0;
+      total += w[c];
+    }
+    const float at = ((float)blockIdx.x + 0.5f) / (float)gridDim.x * total;
+    int c0 = 0;
+    float acc = 0.f;
+#pragma unroll
+    for (int c = 0; c < MIX_MAX_CODES; ++c) {
+      if (acc > at || w[c] <= 0.f) continue;
+      c0 = c;
+      acc += w[c];
+    }
+    for (int i = 0; i < m.n_codes; ++i) {
+      const int c = (c0 + i) % m.n_codes;
+      // skip the table set-up of a code whose tasks are all taken (counts read
+      // afresh for every code after the first)
+      long long rem = 0, nt = 0;
+#pragma unroll
+      for (int cc = 0; cc < MIX_MAX_CODES; ++cc)
+        if (cc == c) {
+          rem = left[cc];
+          nt = ntask[cc];
+        }
+      if (i > 0 && rem > 0) {
+        long long t = 0;
+        if (lane == 0) t = phase_taken<MODE>(m.code[c]);
+        rem = nt - bcast0ll(t);
+      }
+      if (rem <= 0) continue;
+      decode_code<Real, IC, IV, W, DV, UL, MODE, false, false, false>(m.code[c], -1, 0);
+    }
   }
 }
 
@@ -959,26 +1016,33 @@ static int run_mode(int what, int mode, bool trace, bool layered, const Args& a,
                  : run_sched<Real, IC, IV, W, DV, UL, false>(what, mode, trace, a, lds, grid, st, out);
 }
 
-template <typename Real, int IC, int IV, int W, int DV, bool UL>
-static int run_mixed(int what, int mode, const MixArgs& m, size_t lds, int grid, hipStream_t st, int* out)
+template <typename Real, int IC, int IV, int W, int DV, bool UL, bool SMALL>
+static int run_mixed_form(int what, int mode, const MixArgs& m, size_t lds, int grid, hipStream_t st, int* out)
 {
   if (what == 1) {
     hipError_t e;
     if (mode == MODE_MAIN)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bpsf_mixed_kernel<Real, IC, IV, W, DV, UL, MODE_MAIN>, 64, lds);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bpsf_mixed_kernel<Real, IC, IV, W, DV, UL, MODE_MAIN, SMALL>, 64, lds);
     else if (mode == MODE_CAND)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bpsf_mixed_kernel<Real, IC, IV, W, DV, UL, MODE_CAND>, 64, lds);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bpsf_mixed_kernel<Real, IC, IV, W, DV, UL, MODE_CAND, SMALL>, 64, lds);
     else
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bpsf_mixed_kernel<Real, IC, IV, W, DV, UL, MODE_EMIT>, 64, lds);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bpsf_mixed_kernel<Real, IC, IV, W, DV, UL, MODE_EMIT, SMALL>, 64, lds);
     return e == hipSuccess ? 0 : -1;
   }
   if (mode == MODE_MAIN)
-    hipLaunchKernelGGL((bpsf_mixed_kernel<Real, IC, IV, W, DV, UL, MODE_MAIN>), dim3(grid), dim3(64), lds, st, m);
+    hipLaunchKernelGGL((bpsf_mixed_kernel<Real, IC, IV, W, DV, UL, MODE_MAIN, SMALL>), dim3(grid), dim3(64), lds, st, m);
   else if (mode == MODE_CAND)
-    hipLaunchKernelGGL((bpsf_mixed_kernel<Real, IC, IV, W, DV, UL, MODE_CAND>), dim3(grid), dim3(64), lds, st, m);
+    hipLaunchKernelGGL((bpsf_mixed_kernel<Real, IC, IV, W, DV, UL, MODE_CAND, SMALL>), dim3(grid), dim3(64), lds, st, m);
   else
-    hipLaunchKernelGGL((bpsf_mixed_kernel<Real, IC, IV, W, DV, UL, MODE_EMIT>), dim3(grid), dim3(64), lds, st, m);
+    hipLaunchKernelGGL((bpsf_mixed_kernel<Real, IC, IV, W, DV, UL, MODE_EMIT, SMALL>), dim3(grid), dim3(64), lds, st, m);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename Real, int IC, int IV, int W, int DV, bool UL>
+static int run_mixed(int what, bool small, int mode, const MixArgs& m, size_t lds, int grid, hipStream_t st, int* out)
+{
+  return small ? run_mixed_form<Real, IC, IV, W, DV, UL, true>(what, mode, m, lds, grid, st, out)
+               : run_mixed_form<Real, IC, IV, W, DV, UL, false>(what, mode, m, lds, grid, st, out);
 }
 
 int family_count()
@@ -1018,17 +1082,17 @@ int tile_dispatch(int what, const TileDesc& t, bool fp64, bool ul, int mode, boo
   return -2;   // no such family compiled
 }
 
-int mixed_dispatch(int what, int fam, bool fp64, bool ul, int mode, const MixArgs& m, size_t lds, int grid,
-                   void* stream, int* out)
+int mixed_dispatch(int what, int fam, bool fp64, bool ul, bool small, int mode, const MixArgs& m, size_t lds,
+                   int grid, void* stream, int* out)
 {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   int i = 0;
 #define BPSF_FAMILY_MIX(IC_, IV_, W_, DV_)                                                        \
   if (i++ == fam) {                                                                               \
-    if (fp64) return ul ? run_mixed<double, IC_, IV_, W_, DV_, true>(what, mode, m, lds, grid, st, out) \
-                        : run_mixed<double, IC_, IV_, W_, DV_, false>(what, mode, m, lds, grid, st, out); \
-    return ul ? run_mixed<float, IC_, IV_, W_, DV_, true>(what, mode, m, lds, grid, st, out)            \
-              : run_mixed<float, IC_, IV_, W_, DV_, false>(what, mode, m, lds, grid, st, out);          \
+    if (fp64) return ul ? run_mixed<double, IC_, IV_, W_, DV_, true>(what, small, mode, m, lds, grid, st, out) \
+                        : run_mixed<double, IC_, IV_, W_, DV_, false>(what, small, mode, m, lds, grid, st, out); \
+    return ul ? run_mixed<float, IC_, IV_, W_, DV_, true>(what, small, mode, m, lds, grid, st, out)            \
+              : run_mixed<float, IC_, IV_, W_, DV_, false>(what, small, mode, m, lds, grid, st, out);          \
   }
   BPSF_FAMILY_LIST(BPSF_FAMILY_MIX)
 #undef BPSF_FAMILY_MIX

@@ -164,9 +164,10 @@ FamilyDesc family_desc(int fam);
 // what = 0: launch; what = 1: *out = resident blocks per CU
 int tile_dispatch(int what, const TileDesc& t, bool fp64, bool uniform_llr, int mode, bool trace,
                   const Args& a, size_t lds_bytes, int grid, void* stream, int* out, bool layered = false);
-// every code of m belongs to family fam
-int mixed_dispatch(int what, int fam, bool fp64, bool uniform_llr, int mode, const MixArgs& m, size_t lds_bytes,
-                   int grid, void* stream, int* out);
+// every code of m belongs to family fam; small: the form for calls of at most
+// 65536 shots (first chunks by rank, kept trial corrections)
+int mixed_dispatch(int what, int fam, bool fp64, bool uniform_llr, bool small, int mode, const MixArgs& m,
+                   size_t lds_bytes, int grid, void* stream, int* out);
 int bucket_launch(const BucketArgs& b, void* stream);
 int wide_count();
 WideDesc wide_desc(int fam);

@@ -103,6 +103,29 @@ def test_mixed_kept_corrections_run_out():
     assert rerun > 0
 
 
+def test_mixed_call_above_the_small_form():
+    """A mixed call of more than 65536 shots runs the large form of the mixed
+    kernel (every chunk from the counters, no kept corrections): every shot
+    equals the single-code call's, the work counters too, and every winner is
+    decoded again."""
+    p = 0.03
+    hs = [codes.get_code(n).hx for n in NAMES]
+    sc, syn, _, _ = shots.mixed_batch(hs, p, 14000, shots.stream_key(shots.MASTER_SEED, 906))
+    assert len(sc) > 65536
+    prm = U.oracle_params(k=6)
+    print(f"mixed f32 {len(sc)} shots", flush=True)
+    out = _mix_decode(hs, sc, syn, [np.full(h.shape[1], p) for h in hs], prm)
+    assert out["bad"] == 0
+    for c, h in enumerate(hs):
+        g, sel = _per_code(out, sc, c, h.shape[1])
+        one = U.gpu_decode(h, syn[sel, :h.shape[0]], p, prm)
+        assert len(U.mismatches(g, one)) == 0, NAMES[c]
+        st = out["stats"][c]
+        for f in ("main_iterations", "trial_iterations", "failed_shots", "converged_trials", "errors"):
+            assert st[f] == one["stats"][f], (NAMES[c], f)
+        assert st["failed_shots"] > 0 and st["rerun_iterations"] > 0 and one["stats"]["rerun_iterations"] == 0
+
+
 def test_mixed_first_success_with_pruning():
     """First success with pruning in one mixed call (trial tasks of every
     code taken trial index first): every shot equals the oracle's, which
