@@ -1332,8 +1332,7 @@ int mix_decode(bpsf_mix m, const int32_t* shot_code, const int64_t* counts, cons
     int per_cu = 0;
     if (occupancy(true, TileDesc{fam, 0}, fp64, uniform, mode, lds, nullptr, &ma, &per_cu, false, small_form))
       return fail(BPSF_EDEVICE, "occupancy query failed for mode %d", mode);
-    // the mixed kernel keeps its per-code wave counts in 16 bits
-    grid[mode] = std::min(per_cu * m->codes[0]->cus, 65535);
+    grid[mode] = per_cu * m->codes[0]->cus;
   }
   if (reset_counters(cnt, (int)words, stream)) return fail(BPSF_EDEVICE, "counter reset launch");
   if (!counts && bucket_launch(b, stream)) return fail(BPSF_EDEVICE, "bucketing launch failed");

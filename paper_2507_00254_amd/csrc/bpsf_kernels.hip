@@ -817,8 +817,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves_per_simd<Real, W, UL, false, false>
       total += w[c];
     }
     // code c (with work) starts the waves whose point lies in [P_c, P_c + w_c),
-    // P_c the work of the codes before it: waves [lo_c, lo_c + nw_c) (the
-    // launch holds fewer than 2^16 waves: nw_c is kept in 16 bits)
+    // P_c the work of the codes before it: waves [lo_c, lo_c + nw_c)
     auto point = [&](int b) { return ((float)b + 0.5f) / (float)gridDim.x * total; };
     auto first_at = [&](float x) {   // first wave whose point is at or past x
       int lo = 0, hi = (int)gridDim.x;

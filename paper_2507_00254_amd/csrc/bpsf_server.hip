@@ -194,11 +194,11 @@ BatchLayout layout_of(const bpsf_server_s* s, int64_t n, size_t scratch)
   return L;
 }
 
-// Room a batched-mode batch adds to its scratch for the corrections that a
-// single-code batch's trials keep (the last phase then copies the winners'
-// instead of decoding them again; 1 MiB keeps about 130 records of a
-// 63-trial small-family decode, every failed shot of a small batch): at most
-// a sixteenth of a caller's device budget.
+// Room a batched-mode batch adds to its scratch for the corrections that its
+// trials keep (the last phase then copies the winners' instead of decoding
+// them again; 1 MiB keeps about 130 records of a 64-trial small-family decode
+// of one code, a fifth of that with five codes in the batch: every failed
+// shot of a small batch): at most a sixteenth of a caller's device budget.
 constexpr size_t KEEP_BYTES = (size_t)1 << 20;
 
 // The device bytes of a batch of n shots (its scratch: the mixed decode's,
