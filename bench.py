@@ -234,6 +234,59 @@ def cpu_baseline(h, syn, p, prm, seconds: float):
 MIXED_NAMES = ("bb72", "bb90", "bb108", "bb144", "bb288")
 
 
+def small_mixed_latency(B, hs, handles, mix, syn, sc, pri, prm, stream, calls):
+    """Latency of small calls on an idle GPU (GPU events, scratch reserved up
+    front, after one untimed call of each kind): a request of U{1..256} shots
+    of one code alone, and two such requests of two codes in one grouped
+    mixed call."""
+    import torch
+    if calls <= 0:
+        return None
+    rng = np.random.default_rng(17)
+    mmax = max(h.shape[0] for h in hs)
+    nmax = max(h.shape[1] for h in hs)
+    rows = [np.nonzero(sc == c)[0] for c in range(len(hs))]
+    g_syn = torch.zeros((512, mmax), dtype=torch.uint8, device="cuda")
+    g_corr = torch.empty((512, nmax), dtype=torch.uint8, device="cuda")
+    g_conv = torch.empty((512,), dtype=torch.uint8, device="cuda")
+    g_it = torch.empty((512,), dtype=torch.int32, device="cuda")
+    # scratch sized up front for the largest such calls: no call grows it
+    for h in handles:
+        B.bpsf_reserve(h, 256, prm)
+    B.bpsf_mix_reserve(mix, 512, prm)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    alone, pair = [], []
+    for i in range(calls + 1):
+        c1, c2 = sorted(int(x) for x in rng.choice(len(hs), 2, replace=False))
+        n1, n2 = (int(x) for x in rng.integers(1, 257, 2))
+        s1 = torch.from_numpy(np.ascontiguousarray(syn[rows[c1][:n1], :hs[c1].shape[0]])).cuda()
+        s2 = torch.from_numpy(np.ascontiguousarray(syn[rows[c2][:n2], :hs[c2].shape[0]])).cuda()
+        g_syn.zero_()
+        g_syn[:n1, :hs[c1].shape[0]] = s1
+        g_syn[n1:n1 + n2, :hs[c2].shape[0]] = s2
+        counts = np.zeros(len(hs), np.int64)
+        counts[c1], counts[c2] = n1, n2
+        o1 = torch.empty((n1, hs[c1].shape[1]), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        B.bpsf_decode(handles[c1], s1, pri[c1], prm, o1, g_conv[:n1], g_it[:n1], stream)
+        ev1.record(stream)
+        ev1.synchronize()
+        t_alone = ev0.elapsed_time(ev1) * 1e3
+        ev0.record(stream)
+        B.bpsf_mix_decode_grouped(mix, counts, g_syn[:n1 + n2], pri, prm, g_corr[:n1 + n2], g_conv[:n1 + n2],
+                                  g_it[:n1 + n2], stream)
+        ev1.record(stream)
+        ev1.synchronize()
+        if i > 0:   # the first of each kind loads its kernels
+            alone.append(t_alone)
+            pair.append(ev0.elapsed_time(ev1) * 1e3)
+    q = lambda v, x: float(np.percentile(np.array(v), x))
+    return {"calls": calls, "request_shots": "U{1..256}",
+            "one_request_us": {"p50": q(alone, 50), "p99": q(alone, 99), "max": float(max(alone))},
+            "two_codes_grouped_us": {"p50": q(pair, 50), "p99": q(pair, 99), "max": float(max(pair))}}
+
+
 def run_mixed(args):
     """Five bivariate-bicycle codes, args.per_code shots each at p, interleaved
     by a seeded permutation, decoded by one bpsf_mix_decode per step; the same
@@ -289,6 +342,7 @@ def run_mixed(args):
     ms_sep = timed(separate_step)
     ms_mix = timed(mixed_step)
     st, bad = B.bpsf_mix_last_stats(mix, len(hs), stream)
+    small = small_mixed_latency(B, hs, handles, mix, syn, sc, pri, prm, stream, args.latency_calls)
     edge_iters = 0
     for c, h in enumerate(hs):
         e = int(h.sum())
@@ -307,6 +361,7 @@ def run_mixed(args):
                                  "frac": lds_gbs / lds_peak()["peak"]},
         "per_code": [{"code": MIXED_NAMES[c], **st[c]} for c in range(len(hs))],
         "invalid_shots": bad,
+        "small_calls": small,
     }
     B.bpsf_mix_free(mix)
     for h in handles:

@@ -1532,6 +1532,22 @@ int bpsf_mix_reserve(bpsf_mix m, int64_t shots, const bpsf_params* p)
       m->records.ensure(sizeof(int32_t) * n * (size_t)stride) || m->keys.ensure(sizeof(unsigned long long) * n) ||
       m->counters.ensure(sizeof(unsigned long long) * ((size_t)CNT_WORDS * m->n + MIX_WORDS)))
     return fail(BPSF_ENOMEM, "scratch for %lld shots", (long long)shots);
+  // the corrections a call of the small form keeps: every code's region at
+  // the most lanes a decode can have
+  if (p->k > 0) {
+    int64_t trials = 1;
+    for (int i = 0; i < m->n; ++i) {
+      TileDesc t;
+      Args a;
+      if (pick_tile(m->codes[i], &t)) return fail(BPSF_ENOTSUP, "code %d has no kernel tile", i);
+      if ((rc = fill_code_args(m->codes[i], p, t, &a))) return rc;
+      trials = std::max<int64_t>(trials, a.n_trials);
+    }
+    const size_t per_rec = sizeof(uint32_t) * (size_t)trials * 64 * (size_t)m->n;
+    const int64_t recs = std::min<int64_t>(std::min(shots, SMALL_CALL_SHOTS), (int64_t)(TRIAL_BITS_MAX / per_rec));
+    if (recs > 0 && m->trial_bits.ensure(per_rec * (size_t)recs, TRIAL_BITS_MAX))
+      return fail(BPSF_ENOMEM, "trial corrections of %lld records", (long long)recs);
+  }
   return 0;
 }
 
