@@ -285,3 +285,45 @@ def test_grouped_call_with_one_code_present():
         B.bpsf_mix_free(mix)
         for x in handles:
             B.bpsf_free_code(x)
+
+
+def test_reserved_mix_small_calls_keep_corrections():
+    """After bpsf_mix_reserve, grouped small calls of growing size (each
+    keeping its trials' corrections) give every shot the single-code call's
+    result, and no winner is decoded again."""
+    import torch
+    from paper_2507_00254_amd import bpsf as B
+    p = 0.05
+    hs = [codes.get_code(n).hx for n in ("bb72", "bb144", "bb288")]
+    prm = U.oracle_params(k=6)
+    handles = [B.bpsf_load_code(h) for h in hs]
+    mix = B.bpsf_mix_create(handles)
+    try:
+        bp = B.make_params(prm.max_iter, prm.cand_max_iter, prm.k, alpha=prm.alpha, precision=B.PREC_FP32)
+        B.bpsf_mix_reserve(mix, 900, bp)
+        pri = [np.full(h.shape[1], p) for h in hs]
+        for r, per in enumerate((40, 120, 300)):
+            sc, syn, _, _ = shots.mixed_batch(hs, p, per, shots.stream_key(shots.MASTER_SEED, 907, r))
+            order = np.argsort(sc, kind="stable")
+            counts = np.bincount(sc, minlength=len(hs))
+            s = torch.from_numpy(np.ascontiguousarray(syn[order])).cuda()
+            n = len(sc)
+            corr = torch.full((n, 288), 7, dtype=torch.uint8, device="cuda")
+            conv = torch.zeros(n, dtype=torch.uint8, device="cuda")
+            it = torch.zeros(n, dtype=torch.int32, device="cuda")
+            B.bpsf_mix_decode_grouped(mix, counts, s, pri, bp, corr, conv, it)
+            torch.cuda.synchronize()
+            st, _ = B.bpsf_mix_last_stats(mix, len(hs))
+            got = {"correction": corr.cpu().numpy(), "converged": conv.cpu().numpy(), "iterations": it.cpu().numpy()}
+            row = 0
+            for c, h in enumerate(hs):
+                g = {k: v[row:row + counts[c]] for k, v in got.items()}
+                g["correction"] = g["correction"][:, :h.shape[1]]
+                one = U.gpu_decode(h, syn[order][row:row + counts[c], :h.shape[0]], p, prm)
+                assert len(U.mismatches(g, one)) == 0, (per, c)
+                assert st[c]["failed_shots"] == one["stats"]["failed_shots"] and st[c]["rerun_iterations"] == 0
+                row += counts[c]
+    finally:
+        B.bpsf_mix_free(mix)
+        for h in handles:
+            B.bpsf_free_code(h)
